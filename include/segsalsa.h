@@ -1,0 +1,165 @@
+/*
+ * segsalsa.h -- C ABI of the MI355X (gfx950) SegSALSA-STR solver.
+ *
+ * SegSALSA-STR (Condessa, Bioucas-Dias, Kovacevic, arXiv 1504.07028) computes
+ * the marginal-MAP hidden field z in R^{K x n} of a segmentation problem,
+ *
+ *     min_z  sum_i -ln(p_i^T z_i) + lambda sum_i ||[J z]_i||_{S_p}       (eq. (7))
+ *     s.t.   z >= 0,  1_K^T z_i = 1,
+ *
+ * where J is the patch-based Jacobian of eq. (4), by the SALSA iteration of
+ * eqs. (12)-(14) applied to the four-term splitting of eqs. (8)-(11).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are class-planar and row-major: element (k, r, c) of a [K][H][W]
+ *    array is at k*H*W + r*W + c.  Pixel i = r*W + c.
+ *  - Pointers are DEVICE pointers owned by the caller unless marked HOST.
+ *    The library allocates no device memory: every call takes a caller
+ *    workspace whose size comes from the matching *_workspace_size query.
+ *  - `precision` selects the element type of every floating-point array:
+ *    float for SEGSALSA_FP32, double for SEGSALSA_FP64.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and returned as a status; the thread-local message is available from
+ *    segsalsa_last_error().  Work is enqueued asynchronously on `stream`
+ *    (a hipStream_t; NULL is the default stream).  A call that is given a
+ *    HOST stats pointer waits for the stream before it returns.
+ *  - No C++ exception crosses this interface.
+ *
+ * Readings of the paper used throughout (the paper is silent or ambiguous):
+ *  - initialisation z^0 = p_i / 1^T p_i (or softmax of logits), all scaled
+ *    multipliers d = 0, u^0 = G z^0;
+ *  - one round = u-update (eq. (13), at the z of the latest z-update) ->
+ *    d-update (eq. (14)) -> z-update (eq. (12)); `iters` rounds return the
+ *    paper's z^{iters+1};
+ *  - D_h, D_v are forward differences with periodic boundaries; P_j shifts
+ *    by the j-th patch offset (dy, dx) in row-major order (dy outer) and
+ *    scales by the caller's multiplier c_j;
+ *  - g4 is the indicator of {1_K^T xi = 1} (eq. (10)): its proximity
+ *    operator is the affine projection; positivity comes from g3.
+ */
+#ifndef SEGSALSA_H
+#define SEGSALSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SEGSALSA_OK = 0,
+  SEGSALSA_ERR_INVALID_ARG = 1,  /* a size, pointer or parameter is out of range        */
+  SEGSALSA_ERR_UNSUPPORTED = 2,  /* valid for the method but not implemented here       */
+  SEGSALSA_ERR_WORKSPACE = 3,    /* workspace NULL, misaligned or smaller than required */
+  SEGSALSA_ERR_DEVICE = 4        /* a HIP call failed (message in segsalsa_last_error)  */
+} segsalsa_status;
+
+typedef enum { SEGSALSA_FP32 = 0, SEGSALSA_FP64 = 1 } segsalsa_precision;
+
+/* Flags reported in segsalsa_stats.flags (set by the device-side input check). */
+#define SEGSALSA_FLAG_NONFINITE_INPUT 1   /* an input value is NaN or infinite          */
+#define SEGSALSA_FLAG_NEGATIVE_PROB 2     /* a probability is negative                  */
+#define SEGSALSA_FLAG_ZERO_PIXEL 4        /* a pixel's probabilities sum to 0            */
+
+/* One problem of eq. (7) and its SALSA parameters. */
+typedef struct {
+  int32_t K;                   /* classes, 2 <= K <= 64                                         */
+  int32_t H, W;                /* image rows and columns, 1 <= H, W <= 4096, H*W >= 2           */
+  int32_t patch_radius;        /* M in [0, 5]: (2M+1) x (2M+1) patch, L = (2M+1)^2 (Sec. 3)     */
+  const double *patch_weights; /* HOST, L finite multipliers c_j of P_j (eq. (4)), row-major in
+                                  (dy, dx) with dy outer; not all zero                            */
+  double schatten_p;           /* 1.0, 2.0 or INFINITY (Sec. 3); anything else -> UNSUPPORTED   */
+  double lambda;               /* prior weight of eq. (6), finite, >= 0                          */
+  double mu;                   /* SALSA penalty of eq. (13), finite, > 0                          */
+  int32_t iters;               /* rounds, >= 0                                                    */
+  int32_t input_is_logits;     /* 0: input holds probabilities (>= 0, finite, positive sum per
+                                  pixel); 1: input holds logits and p = softmax over classes      */
+  int32_t residual_every;      /* > 0: compute primal/dual residuals every that many rounds and
+                                  report the last ones in stats (needs a HOST stats pointer)     */
+  double tol;                  /* > 0: stop after the first checked round whose primal and dual
+                                  residuals are both <= tol (the paper's stopping rule, Sec. 4);
+                                  needs residual_every > 0.  0: run exactly `iters` rounds        */
+  int32_t warm_start;          /* 0: initialise the state from the input.  1: continue from the
+                                  state already in the workspace and z_out, left there by an
+                                  earlier call with the same problem, precision and workspace     */
+} segsalsa_problem;
+
+/* Results reported to a HOST stats pointer. */
+typedef struct {
+  double primal_res;   /* ||G z - u||_F of the last checked round (0 if never checked)        */
+  double dual_res;     /* mu ||G (z_new - z_old)||_F of the last checked round                */
+  double objective;    /* eq. (7) at the projection of z onto the simplex, if requested      */
+  int32_t rounds_done; /* rounds executed by this call                                       */
+  int32_t flags;       /* SEGSALSA_FLAG_* bits from the input check of the initialisation    */
+} segsalsa_stats;
+
+/* Human-readable name of a status code (static string). */
+const char *segsalsa_status_string(segsalsa_status s);
+
+/* Message describing the last error returned on the calling thread ("" if none). */
+const char *segsalsa_last_error(void);
+
+/*
+ * Bytes of device workspace that segsalsa_str_solve needs for `prob` at
+ * `precision`.  Depends only on K, H, W, patch_radius and precision.
+ * Errors: INVALID_ARG / UNSUPPORTED as segsalsa_str_solve would return them.
+ */
+segsalsa_status segsalsa_str_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
+                                            size_t *bytes /* HOST, out */);
+
+/*
+ * Run prob->iters rounds of SALSA for SegSALSA-STR (Sec. 4, eqs. (12)-(14)).
+ *
+ *   input      [K][H][W] probabilities p(x_i | y_i = k) (eq. (7)) or logits; read only.
+ *   z_out      [K][H][W] hidden field after the last round; must not alias input.
+ *              With warm_start it must hold the z of the previous call on entry.
+ *   workspace  >= segsalsa_str_workspace_size bytes, 256-byte aligned; holds the
+ *              solver state (normalised p, scaled multipliers d1..d4) between
+ *              warm-started calls.
+ *   stats      HOST, may be NULL.  When given, the call waits for `stream` and
+ *              fills it.  Required when residual_every > 0 or tol > 0.
+ *
+ * Invalid probabilities (negative, non-finite, zero-sum pixels) are not
+ * detected on the host; the device check sets stats->flags and the result
+ * is then undefined.
+ */
+segsalsa_status segsalsa_str_solve(const segsalsa_problem *prob, segsalsa_precision precision,
+                                   const void *input, void *z_out, void *workspace, size_t workspace_bytes,
+                                   segsalsa_stats *stats, hipStream_t stream);
+
+/*
+ * Labels y_i = argmax_k z_ki, lowest k on ties (the segmentation read out of
+ * the hidden field, Fig. 1).  z [K][H][W], labels [H][W] int32.
+ */
+segsalsa_status segsalsa_str_labels(int32_t K, int32_t H, int32_t W, segsalsa_precision precision,
+                                    const void *z, int32_t *labels, hipStream_t stream);
+
+/*
+ * Copy the solver state held in `workspace` after a solve into canonical
+ * layouts: d1, d3, d4 as [K][H][W] and d2 as [L][2][K][H][W] (offset j,
+ * direction h/v, class, row, column), the scaled multipliers of the four
+ * splits of eq. (11).  Any output pointer may be NULL to skip it.
+ */
+segsalsa_status segsalsa_str_state_export(const segsalsa_problem *prob, segsalsa_precision precision,
+                                          const void *workspace, size_t workspace_bytes, void *d1, void *d2,
+                                          void *d3, void *d4, hipStream_t stream);
+
+/*
+ * Load a state (normalised probabilities p_hat [K][H][W] and d1..d4 in the
+ * layouts of segsalsa_str_state_export) into `workspace`, so that a
+ * following warm-started solve continues from it (with z in z_out).
+ * All four d pointers and p_hat are required.
+ */
+segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa_precision precision,
+                                          void *workspace, size_t workspace_bytes, const void *p_hat,
+                                          const void *d1, const void *d2, const void *d3, const void *d4,
+                                          hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEGSALSA_H */

@@ -1,0 +1,371 @@
+// z-update of SegSALSA-STR (eq. (12)) as a periodic deconvolution.
+//
+// G^T G = 3 I + J^T J and, because the periodic shifts P_j are orthogonal,
+// J^T J = (sum_j c_j^2) (D_h^T D_h + D_v^T D_v).  The operator is therefore a
+// circulant (cyclic convolution, Sec. 4) with the real, even symbol
+//     A(ky, kx) = 3 + Wsum (4 sin^2(pi kx / W) + 4 sin^2(pi ky / H)),
+// and z = IDFT2[ DFT2(rhs) / A ] for each class image.  Two real class images
+// are packed as the real and imaginary parts of one complex image (the symbol
+// is real and even, so the two results come back in the real and imaginary
+// parts of the inverse transform).
+//
+// Three passes over HBM per round:
+//   rows_fwd : sums the grown-tile partial right-hand sides of the prox
+//              kernel (fold), packs class pairs, DFT along rows
+//   cols     : DFT along columns, divide by the symbol (and by H W), inverse
+//              DFT along columns
+//   rows_inv : inverse DFT along rows, unpack into z
+// Each 1-D transform runs in LDS as a mixed-radix Stockham FFT (radix 2, 3,
+// 4, 5, 8 butterflies in registers; any other prime factor as a direct DFT
+// stage).  Twiddles come from exactly rounded tables built once per solve.
+#include "segsalsa_internal.h"
+#include "segsalsa_kernels.h"
+
+namespace segsalsa {
+
+template <typename T>
+__device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ inline C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by +i (sg = +1) or -i (sg = -1)
+template <typename T>
+__device__ inline C2<T> cmuli(C2<T> a, T sg) { return {-sg * a.y, sg * a.x}; }
+// a * w (forward) or a * conj(w) (inverse)
+template <typename T>
+__device__ inline C2<T> twmul(C2<T> a, C2<T> w, bool inv) {
+  const T wy = inv ? -w.y : w.y;
+  return {a.x * w.x - a.y * wy, a.x * wy + a.y * w.x};
+}
+
+// DFT of R values, y_q = sum_r v_r exp(sg 2 pi i r q / R), sg = -1 forward, +1 inverse.
+template <typename T, int R>
+struct Bfly;
+
+template <typename T>
+struct Bfly<T, 2> {
+  __device__ static void run(C2<T>* v, T) {
+    const C2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <typename T>
+struct Bfly<T, 3> {
+  __device__ static void run(C2<T>* v, T sg) {
+    const T h = T(0.86602540378443864676);  // sin(2 pi / 3)
+    const C2<T> t = cadd(v[1], v[2]);
+    const C2<T> d = csub(v[1], v[2]);
+    const C2<T> m = {v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+    const C2<T> e = cmuli(cscale(d, h), sg);
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, e);
+    v[2] = csub(m, e);
+  }
+};
+
+template <typename T>
+struct Bfly<T, 4> {
+  __device__ static void run(C2<T>* v, T sg) {
+    const C2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const C2<T> t2 = cadd(v[1], v[3]), t3 = cmuli(csub(v[1], v[3]), sg);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <typename T>
+struct Bfly<T, 5> {
+  __device__ static void run(C2<T>* v, T sg) {
+    const T c1 = T(0.30901699437494742410);   // cos(2 pi / 5)
+    const T c2 = T(-0.80901699437494742410);  // cos(4 pi / 5)
+    const T s1 = T(0.95105651629515357212);   // sin(2 pi / 5)
+    const T s2 = T(0.58778525229247312917);   // sin(4 pi / 5)
+    const C2<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const C2<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const C2<T> b1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    const C2<T> b2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    const C2<T> e1 = cmuli(C2<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, sg);
+    const C2<T> e2 = cmuli(C2<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, sg);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(b1, e1);
+    v[4] = csub(b1, e1);
+    v[2] = cadd(b2, e2);
+    v[3] = csub(b2, e2);
+  }
+};
+
+template <typename T>
+struct Bfly<T, 8> {
+  __device__ static void run(C2<T>* v, T sg) {
+    const T r = T(0.70710678118654752440);  // 1/sqrt(2)
+    C2<T> e[4] = {v[0], v[2], v[4], v[6]};
+    C2<T> o[4] = {v[1], v[3], v[5], v[7]};
+    Bfly<T, 4>::run(e, sg);
+    Bfly<T, 4>::run(o, sg);
+    // o_q *= exp(sg 2 pi i q / 8)
+    const C2<T> o1 = {r * (o[1].x - sg * o[1].y), r * (o[1].y + sg * o[1].x)};
+    const C2<T> o2 = cmuli(o[2], sg);
+    const C2<T> o3 = {r * (-o[3].x - sg * o[3].y), r * (-o[3].y + sg * o[3].x)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// One Stockham stage with a register butterfly of radix R, in place in LDS.
+// nb transforms of length N; element i of transform b sits at b*bs + i*es.
+// Ns is the product of the radices of the previous stages.
+template <typename T, int R>
+__device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* __restrict__ tw, int Ns,
+                          bool inv) {
+  constexpr int IT = (kFftEpt + R - 1) / R;
+  const T sg = inv ? T(1) : T(-1);
+  const int NR = N / R;
+  const int total = nb * NR;
+  const int stw = N / (Ns * R);
+  C2<T> v[IT][R];
+  int ob[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = threadIdx.x + it * blockDim.x;
+    ob[it] = -1;
+    if (item < total) {
+      const int b = item / NR, j = item - b * NR;
+      const int k = j % Ns;
+      const int base = b * bs;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = buf[base + (j + r * NR) * es];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[it][r] = twmul(v[it][r], tw[k * r * stw], inv);
+      }
+      Bfly<T, R>::run(v[it], sg);
+      ob[it] = base + ((j - k) * R + k) * es;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    if (ob[it] >= 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[ob[it] + r * Ns * es] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Stockham stage of any radix R as a direct DFT: one output per work item.
+template <typename T>
+__device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* __restrict__ tw,
+                              int Ns, bool inv) {
+  const int NR = N / R;
+  const int total = nb * N;
+  const int stw = N / (Ns * R);
+  C2<T> out[kFftEpt];
+  int oi[kFftEpt];
+#pragma unroll
+  for (int it = 0; it < kFftEpt; ++it) {
+    const int item = threadIdx.x + it * blockDim.x;
+    oi[it] = -1;
+    if (item < total) {
+      const int b = item / N, rem = item - b * N;
+      const int j = rem / R, q = rem - j * R;
+      const int k = j % Ns;
+      const int base = b * bs;
+      const int st1 = k * stw;
+      const int st2 = q * NR;
+      int e1 = 0, e2 = 0;
+      C2<T> s = {T(0), T(0)};
+      for (int r = 0; r < R; ++r) {
+        int e = e1 + e2;
+        if (e >= N) e -= N;
+        s = cadd(s, twmul(buf[base + (j + r * NR) * es], tw[e], inv));
+        e1 += st1;
+        e2 += st2;
+        if (e2 >= N) e2 -= N;
+      }
+      out[it] = s;
+      oi[it] = base + ((j - k) * R + k + q * Ns) * es;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kFftEpt; ++it)
+    if (oi[it] >= 0) buf[oi[it]] = out[it];
+  __syncthreads();
+}
+
+// Unnormalised DFT (inv = false: exp(-2 pi i ...); inv = true: exp(+2 pi i ...)).
+template <typename T>
+__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* __restrict__ tw,
+                        bool inv) {
+  int Ns = 1;
+  for (int s = 0; s < p.nst; ++s) {
+    const int R = p.rad[s];
+    switch (R) {
+      case 2: stage_reg<T, 2>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 3: stage_reg<T, 3>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 4: stage_reg<T, 4>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 5: stage_reg<T, 5>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 8: stage_reg<T, 8>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      default: stage_generic<T>(buf, p.N, R, nb, es, bs, tw, Ns, inv); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Right-hand side at (k, r, c): the sum over every tile whose grown region
+// covers (r, c) (periodically) of its partial sum there.  A source pixel
+// scatters to rows r_s + [-M, M+1], so only tiles holding source rows in
+// r - M - 1 .. r + M (and likewise columns) can contribute.
+template <typename T>
+__device__ T fold_value(const T* __restrict__ acc, const TileGeom& g, int K, int k, int r, int c) {
+  const int M = g.M;
+  T sum = T(0);
+  for (int d = -M - 1; d <= M; ++d) {
+    const int trr = g.trow(wrap_index(r + d, g.H));
+    bool seen = false;
+    for (int d2 = -M - 1; d2 < d; ++d2) seen |= (g.trow(wrap_index(r + d2, g.H)) == trr);
+    if (seen) continue;
+    const int rr0 = g.r0(trr);
+    const int erlim = g.th(trr) + 2 * M;
+    for (int er = wrap_index(r - rr0 + M, g.H); er <= erlim; er += g.H) {
+      for (int e = -M - 1; e <= M; ++e) {
+        const int tcc = g.tcol(wrap_index(c + e, g.W));
+        bool seenc = false;
+        for (int e2 = -M - 1; e2 < e; ++e2) seenc |= (g.tcol(wrap_index(c + e2, g.W)) == tcc);
+        if (seenc) continue;
+        const int cc0 = g.c0(tcc);
+        const int eclim = g.tw(tcc) + 2 * M;
+        const size_t base = (((size_t)(trr * g.ntc + tcc)) * K + k) * g.ER * g.EC + (size_t)er * g.EC;
+        for (int ec = wrap_index(c - cc0 + M, g.W); ec <= eclim; ec += g.W) sum += acc[base + ec];
+      }
+    }
+  }
+  return sum;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int H = a.g.H, W = a.g.W;
+  const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
+  const int m = blockIdx.x / nrb;
+  const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
+  const int nb = min(a.rows_per_block, H - row0);
+  const int k0 = 2 * m, k1 = 2 * m + 1;
+  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    const int rr = idx / W, c = idx - rr * W;
+    const int r = row0 + rr;
+    C2<T> v;
+    v.x = fold_value(a.acc, a.g, a.K, k0, r, c);
+    v.y = k1 < a.K ? fold_value(a.acc, a.g, a.K, k1, r, c) : T(0);
+    buf[idx] = v;
+  }
+  __syncthreads();
+  fft_lds(buf, a.plan, nb, 1, W, a.tw, false);
+  C2<T>* out = a.spec + ((size_t)m * H + row0) * W;
+  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) out[idx] = buf[idx];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int H = a.H, W = a.W;
+  const int CB = a.cols_per_block;
+  const int ncb = (W + CB - 1) / CB;
+  const int m = blockIdx.x / ncb;
+  const int col0 = (blockIdx.x - m * ncb) * CB;
+  const int nb = min(CB, W - col0);
+  C2<T>* sp = a.spec + (size_t)m * H * W + col0;
+  for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
+    const int y = idx / nb, j = idx - y * nb;
+    buf[idx] = sp[(size_t)y * W + j];
+  }
+  __syncthreads();
+  fft_lds(buf, a.plan, nb, nb, 1, a.tw, false);
+  for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
+    const int y = idx / nb, j = idx - y * nb;
+    const double inv = a.scale / (3.0 + a.wsum * (a.sx[col0 + j] + a.sy[y]));
+    buf[idx] = cscale(buf[idx], T(inv));
+  }
+  __syncthreads();
+  fft_lds(buf, a.plan, nb, nb, 1, a.tw, true);
+  for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
+    const int y = idx / nb, j = idx - y * nb;
+    sp[(size_t)y * W + j] = buf[idx];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int H = a.H, W = a.W;
+  const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
+  const int m = blockIdx.x / nrb;
+  const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
+  const int nb = min(a.rows_per_block, H - row0);
+  const C2<T>* in = a.spec + ((size_t)m * H + row0) * W;
+  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) buf[idx] = in[idx];
+  __syncthreads();
+  fft_lds(buf, a.plan, nb, 1, W, a.tw, true);
+  const int k0 = 2 * m, k1 = 2 * m + 1;
+  T* z0 = a.z + ((size_t)k0 * H + row0) * W;
+  T* z1 = a.z + ((size_t)k1 * H + row0) * W;
+  const bool has1 = k1 < a.K;
+  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
+    const C2<T> v = buf[idx];
+    z0[idx] = v.x;
+    if (has1) z1[idx] = v.y;
+  }
+}
+
+template <typename K, typename A>
+static hipError_t launch_fft(K fn, const A& a, int blocks, int threads, size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static int row_blocks(int H, int rpb, int P) { return P * ((H + rpb - 1) / rpb); }
+
+hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_rows_fwd_kernel<float>, a, row_blocks<float>(a.g.H, a.rows_per_block, a.P), threads, lds, st);
+}
+hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_rows_fwd_kernel<double>, a, row_blocks<double>(a.g.H, a.rows_per_block, a.P), threads, lds,
+                    st);
+}
+hipError_t launch_cols(const ColArgs<float>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_cols_kernel<float>, a, a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block), threads,
+                    lds, st);
+}
+hipError_t launch_cols(const ColArgs<double>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_cols_kernel<double>, a, a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block), threads,
+                    lds, st);
+}
+hipError_t launch_rows_inv(const RowInvArgs<float>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_rows_inv_kernel<float>, a, row_blocks<float>(a.H, a.rows_per_block, a.P), threads, lds, st);
+}
+hipError_t launch_rows_inv(const RowInvArgs<double>& a, int threads, size_t lds, hipStream_t st) {
+  return launch_fft(fft_rows_inv_kernel<double>, a, row_blocks<double>(a.H, a.rows_per_block, a.P), threads, lds,
+                    st);
+}
+
+}  // namespace segsalsa

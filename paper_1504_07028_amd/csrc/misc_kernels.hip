@@ -1,0 +1,195 @@
+// Set-up, initialisation, layout conversion and read-out kernels.
+#include "segsalsa_internal.h"
+#include "segsalsa_kernels.h"
+
+namespace segsalsa {
+
+// Twiddle tables exp(-2 pi i t / N) and the 1-D symbols 4 sin^2(pi t / N) of
+// D^T D (periodic forward difference), in FP64 then rounded to T.
+template <typename T>
+__global__ void setup_kernel(const SetupArgs<T> a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < a.W) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)a.W, &s, &c);
+    a.twW[t] = C2<T>{T(c), T(-s)};
+    const double h = sinpi((double)t / (double)a.W);
+    a.sx[t] = 4.0 * h * h;
+  }
+  if (t < a.H) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)a.H, &s, &c);
+    a.twH[t] = C2<T>{T(c), T(-s)};
+    const double h = sinpi((double)t / (double)a.H);
+    a.sy[t] = 4.0 * h * h;
+  }
+}
+
+template <typename T>
+hipError_t launch_setup_t(const SetupArgs<T>& a, hipStream_t st) {
+  const int n = a.W > a.H ? a.W : a.H;
+  hipLaunchKernelGGL(setup_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_setup(const SetupArgs<float>& a, hipStream_t st) { return launch_setup_t(a, st); }
+hipError_t launch_setup(const SetupArgs<double>& a, hipStream_t st) { return launch_setup_t(a, st); }
+
+// Position of pixel (r, c) in the tile layout: (tile, step, lane).
+__device__ inline void tile_pos(const TileGeom& g, int r, int c, int& tile, int& step, int& lane) {
+  const int tr = g.trow(r), tc = g.tcol(c);
+  const int f = (r - g.r0(tr)) * g.tw(tc) + (c - g.c0(tc));
+  tile = tr * g.ntc + tc;
+  step = f >> 6;
+  lane = f & 63;
+}
+
+// Initial state: p_hat = p / 1^T p (or softmax of logits), z = p_hat, d1 = d3 = d4 = 0.
+template <typename T>
+__global__ void init_kernel(const InitArgs<T> a) {
+  const int H = a.g.H, W = a.g.W, K = a.K;
+  const size_t n = (size_t)H * W;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = (int)(i / W), c = (int)(i - (size_t)r * W);
+  int flags = 0;
+  double mx = -1.0 / 0.0;
+  double sum = 0.0;
+  if (a.is_logits) {
+    for (int k = 0; k < K; ++k) {
+      const double x = (double)a.input[(size_t)k * n + i];
+      if (!isfinite(x)) flags |= 1;
+      mx = fmax(mx, x);
+    }
+    for (int k = 0; k < K; ++k) sum += exp((double)a.input[(size_t)k * n + i] - mx);
+  } else {
+    for (int k = 0; k < K; ++k) {
+      const double x = (double)a.input[(size_t)k * n + i];
+      if (!isfinite(x)) flags |= 1;
+      if (x < 0.0) flags |= 2;
+      sum += x;
+    }
+  }
+  if (!(sum > 0.0)) flags |= 4;
+  const double inv = 1.0 / sum;
+  int tile, step, lane;
+  tile_pos(a.g, r, c, tile, step, lane);
+  const size_t sb = ((size_t)tile * a.g.steps + step) * K;
+  for (int k = 0; k < K; ++k) {
+    const double x = (double)a.input[(size_t)k * n + i];
+    const T ph = T(a.is_logits ? exp(x - mx) * inv : x * inv);
+    a.z[(size_t)k * n + i] = ph;
+    a.phat[(sb + k) * 64 + lane] = ph;
+    a.dm[((sb + k) * 3 + 0) * 64 + lane] = T(0);
+    a.dm[((sb + k) * 3 + 1) * 64 + lane] = T(0);
+    a.dm[((sb + k) * 3 + 2) * 64 + lane] = T(0);
+  }
+  if (flags) atomicOr(a.flags, flags);
+}
+
+template <typename T>
+hipError_t launch_init_t(const InitArgs<T>& a, hipStream_t st) {
+  const size_t n = (size_t)a.g.H * a.g.W;
+  hipLaunchKernelGGL(init_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_init(const InitArgs<float>& a, hipStream_t st) { return launch_init_t(a, st); }
+hipError_t launch_init(const InitArgs<double>& a, hipStream_t st) { return launch_init_t(a, st); }
+
+__global__ void fill_zero_kernel(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const size_t ntail = bytes - n16 * 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4*>(p), n16,
+                     reinterpret_cast<unsigned char*>(p) + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+// Tile layout <-> canonical layouts, one thread per (pixel, class).
+template <typename T>
+__global__ void state_kernel(const StateArgs<T> a) {
+  const int H = a.g.H, W = a.g.W, K = a.K, L = a.L;
+  const size_t n = (size_t)H * W;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * K) return;
+  const int k = (int)(gid / n);
+  const size_t i = gid - (size_t)k * n;
+  const int r = (int)(i / W), c = (int)(i - (size_t)r * W);
+  int tile, step, lane;
+  tile_pos(a.g, r, c, tile, step, lane);
+  const size_t kb = ((size_t)tile * a.g.steps + step) * K + k;
+  const size_t ci = (size_t)k * n + i;
+  if (a.to_canonical) {
+    if (a.phat) a.phat[ci] = a.phat_t[kb * 64 + lane];
+    if (a.d1) a.d1[ci] = a.dm_t[(kb * 3 + 0) * 64 + lane];
+    if (a.d3) a.d3[ci] = a.dm_t[(kb * 3 + 1) * 64 + lane];
+    if (a.d4) a.d4[ci] = a.dm_t[(kb * 3 + 2) * 64 + lane];
+    if (a.d2) {
+      for (int j = 0; j < L; ++j) {
+        const C2<T> v = reinterpret_cast<const C2<T>*>(a.d2_t)[(kb * L + j) * 64 + lane];
+        a.d2[((size_t)(j * 2 + 0) * K + k) * n + i] = v.x;
+        a.d2[((size_t)(j * 2 + 1) * K + k) * n + i] = v.y;
+      }
+    }
+  } else {
+    a.phat_t[kb * 64 + lane] = a.phat[ci];
+    a.dm_t[(kb * 3 + 0) * 64 + lane] = a.d1[ci];
+    a.dm_t[(kb * 3 + 1) * 64 + lane] = a.d3[ci];
+    a.dm_t[(kb * 3 + 2) * 64 + lane] = a.d4[ci];
+    for (int j = 0; j < L; ++j) {
+      C2<T> v;
+      v.x = a.d2[((size_t)(j * 2 + 0) * K + k) * n + i];
+      v.y = a.d2[((size_t)(j * 2 + 1) * K + k) * n + i];
+      reinterpret_cast<C2<T>*>(a.d2_t)[(kb * L + j) * 64 + lane] = v;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_state_t(const StateArgs<T>& a, hipStream_t st) {
+  const size_t tot = (size_t)a.g.H * a.g.W * a.K;
+  hipLaunchKernelGGL(state_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_state(const StateArgs<float>& a, hipStream_t st) { return launch_state_t(a, st); }
+hipError_t launch_state(const StateArgs<double>& a, hipStream_t st) { return launch_state_t(a, st); }
+
+// Segmentation read-out: argmax over classes, lowest class on ties.
+template <typename T>
+__global__ void labels_kernel(int K, size_t n, const T* __restrict__ z, int32_t* __restrict__ lab) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T best = z[i];
+  int arg = 0;
+  for (int k = 1; k < K; ++k) {
+    const T v = z[(size_t)k * n + i];
+    if (v > best) {
+      best = v;
+      arg = k;
+    }
+  }
+  lab[i] = arg;
+}
+
+template <typename T>
+hipError_t launch_labels_t(int K, int H, int W, const T* z, int32_t* lab, hipStream_t st) {
+  const size_t n = (size_t)H * W;
+  hipLaunchKernelGGL(labels_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, n, z, lab);
+  return hipGetLastError();
+}
+hipError_t launch_labels(int K, int H, int W, const float* z, int32_t* lab, hipStream_t st) {
+  return launch_labels_t(K, H, W, z, lab, st);
+}
+hipError_t launch_labels(int K, int H, int W, const double* z, int32_t* lab, hipStream_t st) {
+  return launch_labels_t(K, H, W, z, lab, st);
+}
+
+}  // namespace segsalsa

@@ -1,0 +1,279 @@
+// Fused per-pixel proximity kernel of one SALSA round (SegSALSA-STR, Sec. 4).
+//
+// One workgroup owns one tile of the image.  Wavefront w handles classes
+// k = w, w + nw, ... for 64 pixels at a time (one pixel per lane).  Per pixel
+// and round it computes, from z and the scaled multipliers d:
+//   g1 (data term, eq. (10)):   u1 = prox_{g1/mu}(z - d1): closed-form root
+//                               of mu t^2 - mu (p^T v) t - ||p||^2 = 0
+//   g2 (Schatten prior):        u2 = prox_{(lambda/mu)||.||_{S_p}}(J z - d2),
+//                               reduced to the 2x2 structure tensor (eq. (5))
+//   g3 (positivity):            u3 = max(z - d3, 0)
+//   g4 (sum to one):            u4 = (z - d4) - (1^T (z - d4) - 1) / K
+// the multiplier update d_j <- u_j - (H_j z - d_j) (eq. (14)), and scatters
+// u_j + d_j through H_j^T into a per-tile accumulator: the right-hand side
+// G^T (u + d) of the normal equations of the z-update (eq. (12)).
+//
+// The J^T scatter of a pixel reaches pixels up to (M, M+1) away, so every
+// tile accumulates over its tile grown by that margin in LDS; the row FFT
+// pass sums the overlapping grown tiles.  A class's accumulator is written by
+// one wavefront only and, within one instruction, lanes hit distinct
+// addresses, so the LDS adds are free of races and their order is fixed.
+#include "segsalsa_internal.h"
+#include "segsalsa_kernels.h"
+
+namespace segsalsa {
+
+// Multiplier N of the Schatten-p proximity operator for one pixel.
+//
+// With S = Y^T Y = [[A, B], [B, C]] the structure tensor of the (LK)x2 block
+// Y, the proximal point is Y V diag(rho) V^T where sigma_+- = sqrt(eig(S)),
+// rho = shrunk(sigma) / sigma (0 where the shrunk value is 0) and V holds the
+// eigenvectors of S.  Written as N = alpha I + beta S with beta the divided
+// difference (rho_+ - rho_-) / (lambda_+ - lambda_-), expressed in closed
+// forms that stay finite and exact as the two eigenvalues merge.
+__device__ inline void schatten_multiplier(double A, double B, double C, double tau, int pkind,
+                                           double& n11, double& n12, double& n22) {
+  if (!(tau > 0.0)) {  // lambda = 0: prox is the identity
+    n11 = 1.0; n12 = 0.0; n22 = 1.0;
+    return;
+  }
+  if (pkind == kSchatten2) {  // Frobenius norm of the block: group shrink
+    const double nrm = sqrt(fmax(A + C, 0.0));
+    const double rho = nrm > tau ? 1.0 - tau / nrm : 0.0;
+    n11 = rho; n12 = 0.0; n22 = rho;
+    return;
+  }
+  const double hs = 0.5 * (A + C);
+  const double hd = 0.5 * (A - C);
+  const double R = sqrt(hd * hd + B * B);   // (lambda_+ - lambda_-) / 2
+  const double lp = hs + R;
+  const double lm = fmax(hs - R, 0.0);
+  const double sp = sqrt(lp), sm = sqrt(lm);
+  double rm, beta;
+  if (pkind == kSchatten1) {  // soft threshold of the singular values
+    if (sm > tau) {
+      rm = 1.0 - tau / sm;
+      beta = tau / (sp * sm * (sp + sm));
+    } else if (sp > tau) {
+      rm = 0.0;
+      beta = (sp - tau) / (sp * 2.0 * R);
+    } else {
+      n11 = 0.0; n12 = 0.0; n22 = 0.0;
+      return;
+    }
+  } else {  // Schatten-inf: sigma minus its projection on the l1 ball of radius tau
+    if (sp + sm <= tau) {
+      n11 = 0.0; n12 = 0.0; n22 = 0.0;
+      return;
+    }
+    if (sp - sm >= tau) {
+      rm = 1.0;
+      beta = -tau / (sp * 2.0 * R);
+    } else {
+      const double th = 0.5 * (sp + sm - tau);
+      rm = th / sm;
+      beta = -th / (sp * sm * (sp + sm));
+    }
+  }
+  const double alpha = rm - beta * lm;
+  n11 = alpha + beta * A;
+  n12 = beta * B;
+  n22 = alpha + beta * C;
+}
+
+// 1 / (mu t) with t > 0 the root of mu t^2 - mu s t - q = 0 (g1 prox, eq. (10)).
+__device__ inline double data_prox_gain(double s, double q, double mu) {
+  const double disc = sqrt(s * s + 4.0 * q / mu);
+  if (s >= 0.0) return 2.0 / (mu * (s + disc));
+  return (disc - s) / (2.0 * q);
+}
+
+template <typename T, int M, int KPW>
+__global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
+prox_rhs_kernel(const ProxArgs<T> a) {
+  constexpr int D = 2 * M + 1;
+  constexpr int L = D * D;
+  const TileGeom& g = a.g;
+  const int tile = blockIdx.x;
+  const int tr = tile / g.ntc;
+  const int tc = tile - tr * g.ntc;
+  const int r0 = g.r0(tr), c0 = g.c0(tc);
+  const int th = g.th(tr), tw = g.tw(tc);
+  const int ER = th + 2 * M + 1, EC = tw + 2 * M + 1;
+  const int plane = ER * EC;
+  const int K = a.K, nw = a.nw;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int H = g.H, W = g.W;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
+  T* acc = zt + K * plane;             // [K][ER][EC] G^T(u + d) partial sums
+  T* part = acc + K * plane;           // [2][6][nw][64] per-class partial sums
+
+  for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
+    const int k = idx / plane;
+    const int rem = idx - k * plane;
+    const int er = rem / EC, ec = rem - er * EC;
+    const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
+    zt[idx] = a.z[((size_t)k * H + gr) * W + gc];
+    acc[idx] = T(0);
+  }
+  __syncthreads();
+
+  const int P = th * tw;
+  const int nsteps = (P + 63) >> 6;
+  for (int s = 0; s < nsteps; ++s) {
+    const int f = (s << 6) + lane;
+    const bool valid = f < P;
+    const int lr = valid ? f / tw : 0;
+    const int lc = valid ? f - lr * tw : 0;
+    const size_t stepbase = ((size_t)tile * g.steps + s) * K;
+
+    T Y[KPW][L][2];
+    T pk[KPW], v1[KPW], v3[KPW], v4[KPW];
+    T ps = T(0), pq = T(0), psv = T(0), pa = T(0), pb = T(0), pc = T(0);
+#pragma unroll
+    for (int kk = 0; kk < KPW; ++kk) {
+      const int k = wid + kk * nw;
+      pk[kk] = v1[kk] = v3[kk] = v4[kk] = T(0);
+      if (k < K && valid) {
+        const size_t kb = stepbase + k;
+        pk[kk] = a.phat[kb * 64 + lane];
+        const T d1 = a.dm[(kb * 3 + 0) * 64 + lane];
+        const T d3 = a.dm[(kb * 3 + 1) * 64 + lane];
+        const T d4 = a.dm[(kb * 3 + 2) * 64 + lane];
+        const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
+        const T zc = zk[0];
+        v1[kk] = zc - d1;
+        v3[kk] = zc - d3;
+        v4[kk] = zc - d4;
+        ps += pk[kk] * v1[kk];
+        pq += pk[kk] * pk[kk];
+        psv += v4[kk];
+        const C2<T>* d2p = reinterpret_cast<const C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          const int dy = j / D - M, dx = j % D - M;
+          const T* zr = zk + dy * EC + dx;
+          const T z00 = zr[0], z01 = zr[1], z10 = zr[EC];
+          const C2<T> dd = d2p[j * 64];
+          const T yh = a.c[j] * (z01 - z00) - dd.x;
+          const T yv = a.c[j] * (z10 - z00) - dd.y;
+          Y[kk][j][0] = yh;
+          Y[kk][j][1] = yv;
+          pa += yh * yh;
+          pb += yh * yv;
+          pc += yv * yv;
+        }
+      }
+    }
+    T* pbuf = part + (size_t)(s & 1) * 6 * nw * 64;
+    pbuf[(0 * nw + wid) * 64 + lane] = ps;
+    pbuf[(1 * nw + wid) * 64 + lane] = pq;
+    pbuf[(2 * nw + wid) * 64 + lane] = psv;
+    pbuf[(3 * nw + wid) * 64 + lane] = pa;
+    pbuf[(4 * nw + wid) * 64 + lane] = pb;
+    pbuf[(5 * nw + wid) * 64 + lane] = pc;
+    __syncthreads();
+    if (valid) {
+    double S = 0.0, Q = 0.0, SV = 0.0, A = 0.0, B = 0.0, C = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      S += (double)pbuf[(0 * nw + w) * 64 + lane];
+      Q += (double)pbuf[(1 * nw + w) * 64 + lane];
+      SV += (double)pbuf[(2 * nw + w) * 64 + lane];
+      A += (double)pbuf[(3 * nw + w) * 64 + lane];
+      B += (double)pbuf[(4 * nw + w) * 64 + lane];
+      C += (double)pbuf[(5 * nw + w) * 64 + lane];
+    }
+    const double gain = data_prox_gain(S, Q, a.mu);
+    const T d4n = T(-(SV - 1.0) / (double)K);
+    double n11, n12, n22;
+    schatten_multiplier(A, B, C, a.tau, a.pkind, n11, n12, n22);
+    const T m11 = T(n11 - 1.0), m12 = T(n12), m22 = T(n22 - 1.0);
+
+#pragma unroll
+    for (int kk = 0; kk < KPW; ++kk) {
+      const int k = wid + kk * nw;
+      if (k < K) {
+        const size_t kb = stepbase + k;
+        const T d1n = T((double)pk[kk] * gain);
+        const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
+        const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
+        a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
+        a.dm[(kb * 3 + 1) * 64 + lane] = d3n;
+        a.dm[(kb * 3 + 2) * 64 + lane] = d4n;
+        T* ak = acc + k * plane + (lr + M) * EC + (lc + M);
+        atomicAdd(ak, own);
+        C2<T>* d2o = reinterpret_cast<C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          const int dy = j / D - M, dx = j % D - M;
+          const T yh = Y[kk][j][0], yv = Y[kk][j][1];
+          const T nh = yh * m11 + yv * m12;  // d2 <- u2 - Y = Y (N - I)
+          const T nv = yh * m12 + yv * m22;
+          C2<T> o;
+          o.x = nh;
+          o.y = nv;
+          d2o[j * 64] = o;
+          const T ah = a.c[j] * (T(2) * nh + yh);  // c_j (u2 + d2): P_j^T then D^T
+          const T av = a.c[j] * (T(2) * nv + yv);
+          T* at = ak + dy * EC + dx;
+          atomicAdd(at, -(ah + av));
+          atomicAdd(at + 1, ah);
+          atomicAdd(at + EC, av);
+        }
+      }
+    }
+    }  // valid
+  }
+  __syncthreads();
+  T* blk = a.acc + (size_t)tile * K * g.ER * g.EC;
+  for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
+    const int k = idx / plane;
+    const int rem = idx - k * plane;
+    const int er = rem / EC, ec = rem - er * EC;
+    blk[((size_t)k * g.ER + er) * g.EC + ec] = acc[idx];
+  }
+}
+
+template <typename T, int M, int KPW>
+static hipError_t launch_prox_t(const ProxArgs<T>& a, size_t lds, hipStream_t st) {
+  auto fn = prox_rhs_kernel<T, M, KPW>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(a.g.ntiles()), dim3(a.nw * 64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t launch_prox_m(const ProxArgs<T>& a, int kpw, size_t lds, hipStream_t st) {
+  switch (kpw) {
+    case 1: return launch_prox_t<T, M, 1>(a, lds, st);
+    case 2: return launch_prox_t<T, M, 2>(a, lds, st);
+    case 4: return launch_prox_t<T, M, 4>(a, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t launch_prox_any(const ProxArgs<T>& a, int kpw, size_t lds, hipStream_t st) {
+  switch (a.g.M) {
+    case 0: return launch_prox_m<T, 0>(a, kpw, lds, st);
+    case 1: return launch_prox_m<T, 1>(a, kpw, lds, st);
+    case 2: return launch_prox_m<T, 2>(a, kpw, lds, st);
+    case 3: return launch_prox_m<T, 3>(a, kpw, lds, st);
+    case 4: return launch_prox_m<T, 4>(a, kpw, lds, st);
+    case 5: return launch_prox_m<T, 5>(a, kpw, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_prox(const ProxArgs<float>& a, int kpw, size_t lds, hipStream_t st) {
+  return launch_prox_any<float>(a, kpw, lds, st);
+}
+hipError_t launch_prox(const ProxArgs<double>& a, int kpw, size_t lds, hipStream_t st) {
+  return launch_prox_any<double>(a, kpw, lds, st);
+}
+
+}  // namespace segsalsa

@@ -1,0 +1,118 @@
+// Internal declarations shared by the SegSALSA-STR HIP kernels and the host runtime.
+//
+// Data layout (device workspace, one image):
+//   The image is cut into a grid of ntr x ntc tiles whose heights (widths)
+//   differ by at most one row (column).  Inside a tile the th*tw pixels are
+//   numbered row-major and grouped in "steps" of 64 consecutive pixels, one
+//   pixel per lane of a wavefront.  Per-pixel solver state is stored
+//   tile-major so that every wavefront load/store is one contiguous block:
+//     phat [tile][step][K][64]          normalised class probabilities
+//     dm   [tile][step][K][3][64]       scaled multipliers d1, d3, d4
+//     d2   [tile][step][K][L][64][2]    J-split multipliers (h, v interleaved)
+//     acc  [tile][K][ER][EC]            per-tile J^T / identity-split partial sums
+//                                       over the tile grown by (M, M+1) on each side
+//   z and the spectrum are class-planar: z [K][H][W], spec [P][H][W] complex
+//   with P = ceil(K/2) (two classes packed as real and imaginary part).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace segsalsa {
+
+constexpr int kWave = 64;
+constexpr int kMaxM = 5;
+constexpr int kMaxL = (2 * kMaxM + 1) * (2 * kMaxM + 1);
+constexpr int kMaxK = 64;
+constexpr int kMaxSide = 4096;
+constexpr int kFftEpt = 16;        // complex elements per thread in one LDS FFT workgroup
+constexpr int kMaxRadices = 24;
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+__host__ __device__ inline int wrap_index(int x, int n) {
+  int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
+// Tile grid of one image.  Tile t covers rows [r0(t), r0(t+1)) and columns
+// [c0(t), c0(t+1)); ER x EC is the largest grown tile (th + 2M + 1) x (tw + 2M + 1).
+struct TileGeom {
+  int H, W, M;
+  int ntr, ntc;
+  int TR, TC;   // largest tile height / width
+  int ER, EC;   // TR + 2M + 1, TC + 2M + 1
+  int steps;    // ceil(TR * TC / 64): steps reserved per tile
+  __host__ __device__ int r0(int t) const { return (int)(((long long)t * H) / ntr); }
+  __host__ __device__ int c0(int t) const { return (int)(((long long)t * W) / ntc); }
+  __host__ __device__ int th(int t) const { return r0(t + 1) - r0(t); }
+  __host__ __device__ int tw(int t) const { return c0(t + 1) - c0(t); }
+  // tile row (column) containing image row (column) x
+  __host__ __device__ int trow(int x) const { return (int)((((long long)x + 1) * ntr - 1) / H); }
+  __host__ __device__ int tcol(int x) const { return (int)((((long long)x + 1) * ntc - 1) / W); }
+  __host__ __device__ int ntiles() const { return ntr * ntc; }
+};
+
+// Per-pixel arithmetic parameters of one round.
+enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3 };
+
+template <typename T>
+struct ProxArgs {
+  TileGeom g;
+  int K;
+  int nw;                     // wavefronts per workgroup
+  const T* __restrict__ z;    // [K][H][W]
+  const T* __restrict__ phat; // tile layout
+  T* __restrict__ dm;
+  T* __restrict__ d2;
+  T* __restrict__ acc;
+  double mu, tau;
+  int pkind;
+  T c[kMaxL];
+};
+
+struct FftPlanDev {
+  int N;
+  int nst;
+  int rad[kMaxRadices];
+};
+
+template <typename T>
+struct RowFwdArgs {
+  TileGeom g;
+  int K, P;
+  int rows_per_block;
+  const T* __restrict__ acc;    // per-tile partial sums
+  C2<T>* __restrict__ spec;     // [P][H][W]
+  const C2<T>* __restrict__ tw; // W twiddles exp(-2 pi i t / W)
+  FftPlanDev plan;
+};
+
+template <typename T>
+struct ColArgs {
+  int H, W, P;
+  int cols_per_block;
+  C2<T>* __restrict__ spec;
+  const C2<T>* __restrict__ tw;   // H twiddles
+  const double* __restrict__ sx;  // 4 sin^2(pi kx / W)
+  const double* __restrict__ sy;  // 4 sin^2(pi ky / H)
+  double wsum;                    // sum_j c_j^2
+  double scale;                   // 1 / (H W)
+  FftPlanDev plan;
+};
+
+template <typename T>
+struct RowInvArgs {
+  int H, W, K, P;
+  int rows_per_block;
+  const C2<T>* __restrict__ spec;
+  T* __restrict__ z;
+  const C2<T>* __restrict__ tw;
+  FftPlanDev plan;
+};
+
+}  // namespace segsalsa

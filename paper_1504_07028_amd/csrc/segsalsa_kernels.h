@@ -1,0 +1,92 @@
+// Kernel launchers of the SegSALSA-STR library (defined in the .hip files).
+#pragma once
+
+#include "segsalsa_internal.h"
+
+namespace segsalsa {
+
+// Largest workgroup the prox kernel instantiation <T, M, KPW> is compiled for:
+// each lane keeps KPW classes x 2L entries of the J-split block in registers,
+// so the wavefronts per SIMD (and hence per workgroup) shrink as L grows.
+template <typename T, int M, int KPW>
+__host__ __device__ constexpr int prox_max_threads() {
+  constexpr int L = (2 * M + 1) * (2 * M + 1);
+  constexpr int vg = KPW * 2 * L * (int)(sizeof(T) / 4) + 48;
+  constexpr int wps = 512 / vg;
+  constexpr int w = wps >= 4 ? 4 : (wps < 1 ? 1 : wps);
+  return w * 4 * 64;
+}
+
+inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
+#define SEG_CASE(MM)                                                                                         \
+  case MM:                                                                                                   \
+    if (fp64) return kpw == 1 ? prox_max_threads<double, MM, 1>() : kpw == 2 ? prox_max_threads<double, MM, 2>() \
+                                                                           : prox_max_threads<double, MM, 4>(); \
+    return kpw == 1 ? prox_max_threads<float, MM, 1>() : kpw == 2 ? prox_max_threads<float, MM, 2>()           \
+                                                                 : prox_max_threads<float, MM, 4>();
+  switch (M) {
+    SEG_CASE(0)
+    SEG_CASE(1)
+    SEG_CASE(2)
+    SEG_CASE(3)
+    SEG_CASE(4)
+    SEG_CASE(5)
+    default: return 0;
+  }
+#undef SEG_CASE
+}
+
+hipError_t launch_prox(const ProxArgs<float>& a, int kpw, size_t lds, hipStream_t st);
+hipError_t launch_prox(const ProxArgs<double>& a, int kpw, size_t lds, hipStream_t st);
+
+hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<float>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<double>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<float>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<double>& a, int threads, size_t lds, hipStream_t st);
+
+// Set-up, initialisation and data-movement kernels (misc_kernels.hip).
+template <typename T>
+struct SetupArgs {
+  int H, W;
+  C2<T>* twW;   // exp(-2 pi i t / W), t < W
+  C2<T>* twH;   // exp(-2 pi i t / H), t < H
+  double* sx;   // 4 sin^2(pi t / W)
+  double* sy;   // 4 sin^2(pi t / H)
+};
+hipError_t launch_setup(const SetupArgs<float>& a, hipStream_t st);
+hipError_t launch_setup(const SetupArgs<double>& a, hipStream_t st);
+
+template <typename T>
+struct InitArgs {
+  TileGeom g;
+  int K;
+  int is_logits;
+  const T* input;   // [K][H][W]
+  T* z;             // [K][H][W]
+  T* phat;          // tile layout
+  T* dm;            // tile layout
+  int* flags;
+};
+hipError_t launch_init(const InitArgs<float>& a, hipStream_t st);
+hipError_t launch_init(const InitArgs<double>& a, hipStream_t st);
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Conversion between the tile layout and canonical class-planar arrays.
+template <typename T>
+struct StateArgs {
+  TileGeom g;
+  int K, L;
+  int to_canonical;   // 1: tile -> canonical, 0: canonical -> tile
+  T* phat_t; T* dm_t; T* d2_t;                      // tile layout (workspace)
+  T* phat; T* d1; T* d2; T* d3; T* d4;              // canonical (may be null)
+};
+hipError_t launch_state(const StateArgs<float>& a, hipStream_t st);
+hipError_t launch_state(const StateArgs<double>& a, hipStream_t st);
+
+hipError_t launch_labels(int K, int H, int W, const float* z, int32_t* labels, hipStream_t st);
+hipError_t launch_labels(int K, int H, int W, const double* z, int32_t* labels, hipStream_t st);
+
+}  // namespace segsalsa

@@ -1,0 +1,210 @@
+"""Python binding of libsegsalsa.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/segsalsa.h) and does nothing but check tensor shapes/dtypes/devices,
+pass raw device pointers and the current HIP stream, and translate status
+codes into exceptions.  All arithmetic runs in the HIP kernels.  PyTorch
+only provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_size_t, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsegsalsa.so")
+
+SEGSALSA_FP32 = 0
+SEGSALSA_FP64 = 1
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "WORKSPACE", 4: "DEVICE"}
+FLAG_NONFINITE_INPUT = 1
+FLAG_NEGATIVE_PROB = 2
+FLAG_ZERO_PIXEL = 4
+
+
+class SegsalsaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"segsalsa {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class segsalsa_problem(ctypes.Structure):
+    _fields_ = [
+        ("K", c_int32), ("H", c_int32), ("W", c_int32), ("patch_radius", c_int32),
+        ("patch_weights", POINTER(c_double)),
+        ("schatten_p", c_double), ("lambda_", c_double), ("mu", c_double),
+        ("iters", c_int32), ("input_is_logits", c_int32), ("residual_every", c_int32),
+        ("tol", c_double), ("warm_start", c_int32),
+    ]
+
+
+class segsalsa_stats(ctypes.Structure):
+    _fields_ = [("primal_res", c_double), ("dual_res", c_double), ("objective", c_double),
+                ("rounds_done", c_int32), ("flags", c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsegsalsa.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1504_07028_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.segsalsa_status_string.argtypes = [c_int32]
+    L.segsalsa_status_string.restype = c_char_p
+    L.segsalsa_last_error.argtypes = []
+    L.segsalsa_last_error.restype = c_char_p
+    L.segsalsa_str_workspace_size.argtypes = [POINTER(segsalsa_problem), c_int32, POINTER(c_size_t)]
+    L.segsalsa_str_workspace_size.restype = c_int32
+    L.segsalsa_str_solve.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                     POINTER(segsalsa_stats), c_void_p]
+    L.segsalsa_str_solve.restype = c_int32
+    L.segsalsa_str_labels.argtypes = [c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]
+    L.segsalsa_str_labels.restype = c_int32
+    L.segsalsa_str_state_export.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_size_t, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p]
+    L.segsalsa_str_state_export.restype = c_int32
+    L.segsalsa_str_state_import.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_size_t, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.segsalsa_str_state_import.restype = c_int32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise SegsalsaError(status, lib().segsalsa_last_error().decode())
+
+
+class Problem:
+    """Parameters of one SegSALSA-STR problem (mirrors segsalsa_problem)."""
+
+    def __init__(self, K, H, W, patch_radius, patch_weights, schatten_p=1.0, lam=1.0, mu=1.0, iters=100,
+                 input_is_logits=False, residual_every=0, tol=0.0, warm_start=False):
+        self.K, self.H, self.W, self.patch_radius = int(K), int(H), int(W), int(patch_radius)
+        self.patch_weights = [float(x) for x in patch_weights]
+        self.schatten_p = float(schatten_p)
+        self.lam, self.mu, self.iters = float(lam), float(mu), int(iters)
+        self.input_is_logits = bool(input_is_logits)
+        self.residual_every, self.tol, self.warm_start = int(residual_every), float(tol), bool(warm_start)
+
+    def c_struct(self):
+        w = (c_double * max(1, len(self.patch_weights)))(*self.patch_weights)
+        s = segsalsa_problem(self.K, self.H, self.W, self.patch_radius, ctypes.cast(w, POINTER(c_double)),
+                             self.schatten_p, self.lam, self.mu, self.iters, int(self.input_is_logits),
+                             self.residual_every, self.tol, int(self.warm_start))
+        s._keep = w  # keep the weights array alive with the struct
+        return s
+
+
+def _prec(dtype) -> int:
+    if dtype == torch.float32:
+        return SEGSALSA_FP32
+    if dtype == torch.float64:
+        return SEGSALSA_FP64
+    raise TypeError(f"dtype {dtype} not supported (float32 or float64)")
+
+
+def _dev_ptr(t, name, dtype=None, numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def segsalsa_str_workspace_size(problem: Problem, precision: int) -> int:
+    n = c_size_t(0)
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_workspace_size(ctypes.byref(s), int(precision), ctypes.byref(n)))
+    return int(n.value)
+
+
+def segsalsa_str_solve(problem: Problem, inp, z_out, workspace, stats: bool = False, stream=None):
+    """Run the rounds on the current stream.  Returns a stats dict if stats=True (then waits)."""
+    prec = _prec(z_out.dtype)
+    nel = problem.K * problem.H * problem.W
+    s = problem.c_struct()
+    pin = _dev_ptr(inp, "input", z_out.dtype, nel) if inp is not None else None
+    pz = _dev_ptr(z_out, "z_out", None, nel)
+    pw = _dev_ptr(workspace, "workspace", torch.uint8)
+    st = segsalsa_stats() if stats else None
+    _check(lib().segsalsa_str_solve(ctypes.byref(s), prec, pin, pz, pw, workspace.numel(),
+                                    ctypes.byref(st) if st is not None else None, _stream(stream)))
+    if st is None:
+        return None
+    return dict(primal_res=st.primal_res, dual_res=st.dual_res, objective=st.objective,
+                rounds_done=st.rounds_done, flags=st.flags)
+
+
+def segsalsa_str_labels(z, labels, stream=None):
+    K, H, W = z.shape
+    _check(lib().segsalsa_str_labels(K, H, W, _prec(z.dtype), _dev_ptr(z, "z"),
+                                     _dev_ptr(labels, "labels", torch.int32, H * W), _stream(stream)))
+
+
+def segsalsa_str_state_export(problem: Problem, workspace, d1=None, d2=None, d3=None, d4=None, dtype=None,
+                              stream=None):
+    dtype = dtype or next(t.dtype for t in (d1, d2, d3, d4) if t is not None)
+    s = problem.c_struct()
+    nel = problem.K * problem.H * problem.W
+    L = (2 * problem.patch_radius + 1) ** 2
+    _check(lib().segsalsa_str_state_export(
+        ctypes.byref(s), _prec(dtype), _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(),
+        _dev_ptr(d1, "d1", dtype, nel), _dev_ptr(d2, "d2", dtype, 2 * L * nel), _dev_ptr(d3, "d3", dtype, nel),
+        _dev_ptr(d4, "d4", dtype, nel), _stream(stream)))
+
+
+def segsalsa_str_state_import(problem: Problem, workspace, p_hat, d1, d2, d3, d4, stream=None):
+    dtype = p_hat.dtype
+    s = problem.c_struct()
+    nel = problem.K * problem.H * problem.W
+    L = (2 * problem.patch_radius + 1) ** 2
+    _check(lib().segsalsa_str_state_import(
+        ctypes.byref(s), _prec(dtype), _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(),
+        _dev_ptr(p_hat, "p_hat", dtype, nel), _dev_ptr(d1, "d1", dtype, nel), _dev_ptr(d2, "d2", dtype, 2 * L * nel),
+        _dev_ptr(d3, "d3", dtype, nel), _dev_ptr(d4, "d4", dtype, nel), _stream(stream)))
+
+
+def solve(probs, patch_weights, patch_radius, schatten_p=1.0, lam=1.0, mu=1.0, iters=100, input_is_logits=False,
+          workspace=None, stats=False):
+    """Convenience wrapper: allocate z and the workspace with torch and run segsalsa_str_solve.
+
+    probs: device tensor [K][H][W] (float32 or float64).  Returns z (and stats if asked).
+    """
+    K, H, W = probs.shape
+    pr = Problem(K, H, W, patch_radius, patch_weights, schatten_p, lam, mu, iters, input_is_logits)
+    prec = _prec(probs.dtype)
+    need = segsalsa_str_workspace_size(pr, prec)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=probs.device)
+    z = torch.empty_like(probs)
+    st = segsalsa_str_solve(pr, probs, z, workspace, stats=stats)
+    return (z, st) if stats else z
+
+
+def patch_count(M: int) -> int:
+    return (2 * M + 1) ** 2
+
+
+INF = math.inf

@@ -1,0 +1,61 @@
+"""Helpers for the GPU tests: seeded inputs, library calls and oracle runs."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import segsalsa_ref as R
+
+FP64_TOL = 1e-9     # GPU FP64 vs FP64 oracle, max-abs
+FP32_TOL = 2e-4     # GPU FP32 vs FP64 oracle, max-abs
+MARGIN = 1e-3       # labels compared where the oracle's top-two margin exceeds this
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_07028_amd import segsalsa as S
+    S.lib()  # fails loudly if the library is missing
+    return S
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def problem_inputs(H, W, K, M, seed, sigma=1.0, bonus=1.5, outliers=0.0, logit_sigma=1.0):
+    probs, logits, labels = synth.make_image(H, W, K, seed, logit_sigma, bonus, outliers)
+    c = synth.gaussian_patch_multipliers(M, sigma)
+    return probs, logits, labels, c
+
+
+def gpu_solve(S, x_np, c, M, p, lam, mu, iters, dtype, logits=False, stats=False):
+    K, H, W = x_np.shape
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).to(device="cuda", dtype=dtype)
+    pr = S.Problem(K, H, W, M, c, p, lam, mu, iters, input_is_logits=logits)
+    ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
+    z = torch.empty_like(x)
+    st = S.segsalsa_str_solve(pr, x, z, ws, stats=stats)
+    torch.cuda.synchronize()
+    return z, ws, pr, st
+
+
+def oracle_solve(x_np, c, M, p, lam, mu, iters, logits=False):
+    return R.solve(x_np, R.Problem(np.asarray(c, dtype=np.float64), M, p, lam, mu), iters, is_logits=logits)
+
+
+def rounded_input(x_np, dtype):
+    """Input as the GPU sees it (FP32-rounded for FP32 runs), upcast to FP64 for the oracle."""
+    if dtype == torch.float32:
+        return x_np.astype(np.float32).astype(np.float64)
+    return x_np
+
+
+def weights_as_seen(c, dtype):
+    if dtype == torch.float32:
+        return np.asarray(c, dtype=np.float32).astype(np.float64)
+    return np.asarray(c, dtype=np.float64)

@@ -1,0 +1,105 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element.
+
+FP64 runs must match the oracle within 1e-9 max-abs; FP32 runs within 2e-4
+(the oracle consumes the FP32-rounded input and multipliers); labels must be
+identical wherever the oracle's top-two margin exceeds 1e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (FP32_TOL, FP64_TOL, MARGIN, gpu_solve, need_gpu, oracle_solve, problem_inputs,
+                        rounded_input, say, weights_as_seen)
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# (H, W, K, M, p, iters): several tiles, ragged tails, odd/prime sides, degenerate sizes
+SMALL_CASES = [
+    (5, 7, 3, 1, 1.0, 6),
+    (4, 4, 2, 0, 2.0, 6),
+    (8, 5, 4, 2, math.inf, 6),
+    (1, 6, 3, 1, 1.0, 5),
+    (6, 1, 2, 1, 1.0, 5),
+    (13, 11, 3, 2, 1.0, 8),
+    (17, 67, 5, 1, 1.0, 8),
+    (29, 131, 9, 2, 1.0, 6),
+    (70, 33, 16, 1, math.inf, 5),
+    (37, 41, 7, 3, 2.0, 4),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("H,W,K,M,p,iters", SMALL_CASES)
+def test_small_grids(H, W, K, M, p, iters, dtype):
+    S = need_gpu()
+    say(f"case H={H} W={W} K={K} M={M} p={p} iters={iters} {dtype}")
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=H * 131 + W * 7 + K)
+    z, *_ = gpu_solve(S, probs, c, M, p, 0.8, 1.3, iters, dtype)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_plain_64x64(dtype):
+    """The 64x64, K = 4, 3x3 patch, Schatten-1, 100-round workload."""
+    S = need_gpu()
+    wl = synth.WORKLOADS["plain_64x64_k4"]
+    d = synth.make_workload(wl)
+    say(f"case {wl.name} {dtype}")
+    z, *_ = gpu_solve(S, d["probs"], d["weights"], wl.M, wl.schatten_p, wl.lam, wl.mu, wl.iters, dtype)
+    zo = oracle_solve(rounded_input(d["probs"], dtype), weights_as_seen(d["weights"], dtype), wl.M,
+                      wl.schatten_p, wl.lam, wl.mu, wl.iters)
+    zg = z.double().cpu().numpy()
+    err = np.max(np.abs(zg - zo))
+    say(f"  max err {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    srt = np.sort(zo, axis=0)
+    sure = (srt[-1] - srt[-2]) > MARGIN
+    assert np.array_equal(np.argmax(zg, axis=0)[sure], np.argmax(zo, axis=0)[sure])
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0, math.inf])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_pines_145_short(p, dtype):
+    """145x145, K = 16, 5x5 patch, lambda = mu = 2: the first 12 rounds, every Schatten p."""
+    S = need_gpu()
+    wl = synth.WORKLOADS["pines_145x145_k16"]
+    d = synth.make_workload(wl)
+    iters = 12
+    say(f"case {wl.name} p={p} iters={iters} {dtype}")
+    z, *_ = gpu_solve(S, d["probs"], d["weights"], wl.M, p, wl.lam, wl.mu, iters, dtype)
+    zo = oracle_solve(rounded_input(d["probs"], dtype), weights_as_seen(d["weights"], dtype), wl.M, p,
+                      wl.lam, wl.mu, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max err {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+def test_logits_and_asymmetric_weights():
+    S = need_gpu()
+    probs, logits, _, _ = problem_inputs(23, 19, 5, 1, seed=77)
+    c = np.array([0.1, 0.9, 0.3, 0.5, 1.0, 0.2, 0.8, 0.4, 0.6])
+    z, *_ = gpu_solve(S, logits, c, 1, 1.0, 0.7, 1.1, 9, torch.float64, logits=True)
+    zo = oracle_solve(logits, c, 1, 1.0, 0.7, 1.1, 9, logits=True)
+    assert np.max(np.abs(z.cpu().numpy() - zo)) <= FP64_TOL
+
+
+def test_zero_rounds_returns_normalised_input():
+    S = need_gpu()
+    probs, _, _, c = problem_inputs(9, 10, 3, 1, seed=5)
+    scaled = probs * 3.7
+    z, *_ = gpu_solve(S, scaled, c, 1, 1.0, 1.0, 1.0, 0, torch.float64)
+    assert np.max(np.abs(z.cpu().numpy() - probs)) <= 1e-14
+
+
+def test_lambda_zero_identity_prox():
+    S = need_gpu()
+    probs, _, _, c = problem_inputs(12, 14, 4, 1, seed=6)
+    z, *_ = gpu_solve(S, probs, c, 1, 1.0, 0.0, 0.5, 7, torch.float64)
+    zo = oracle_solve(probs, c, 1, 1.0, 0.0, 0.5, 7)
+    assert np.max(np.abs(z.cpu().numpy() - zo)) <= FP64_TOL
