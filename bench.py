@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the SegSALSA-STR SALSA loop on one MI355X.
+
+One step = one call of segsalsa_str_solve on the workload: initialisation and
+all rounds (proximity operators, multiplier updates, J^T scatter, FFT z-solve),
+inputs resident in device memory.  The metric is pixel*class*rounds per second.
+The FP32 path is the headline; it counts only if its z is within 2e-4
+(max-abs) of the FP64 path on the same input (the FP64 path is pinned to the
+FP64 CPU oracle by the GPU tests).  Printed as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel·class·iterations/sec of SALSA-STR loop, FP32 vs FP64 at z err ≤2e-4"
+UNIT = "pixel·class·iterations/s"
+HBM_PEAK_GBS = 8000.0
+Z_TOL = 2e-4
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1504_07028_amd/csrc/prox_kernel.hip", "paper_1504_07028_amd/csrc/segsalsa_internal.h",
+                  "paper_1504_07028_amd/csrc/segsalsa_kernels.h", "paper_1504_07028_amd/csrc/api.hip"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def prox_bytes_per_unit(L: int, b: int) -> int:
+    """Algorithmic bytes of the fused prox kernel per pixel*class: d2 read+write (4L words),
+    d1/d3/d4 read+write (6), p_hat read (1), z read (1), right-hand side write (1)."""
+    return (4 * L + 9) * b
+
+
+def load_traffic(workload: str, dtype: str, src_hash: str):
+    """Measured HBM bytes per prox launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(PROFILE_DIR, f"prox_{workload}_{dtype}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != src_hash:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def time_solves(S, torch, pr, x, z, ws, steps, warmup):
+    for _ in range(warmup):
+        S.segsalsa_str_solve(pr, x, z, ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        S.segsalsa_str_solve(pr, x, z, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def cpu_baseline(wl, probs, weights, budget_s: float):
+    """The FP64 oracle on the same input, timed on this host for a bounded number of rounds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import segsalsa_ref as R
+    pr = R.Problem(np.asarray(weights, dtype=np.float64), wl.M, wl.schatten_p, wl.lam, wl.mu)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        st, ph = R.solve(probs, pr, 1, return_state=True)
+        t1 = time.perf_counter() - t0
+        rounds = int(max(1, min(wl.iters, budget_s / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        R.solve(probs, pr, rounds)
+        dt = time.perf_counter() - t0
+    units = wl.n * wl.K * rounds
+    return dict(value=units / dt, unit=UNIT, cores=1, kind="oracle",
+                sample=f"{wl.name}: {rounds} of {wl.iters} rounds from the initial state, FP64 numpy, "
+                       f"1 thread (BLAS/FFT limited to 1), {dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pines_145x145_k16")
+    ap.add_argument("--schatten-p", type=float, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the solver "
+              "shards nothing across GPUs).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1504_07028_amd import segsalsa as S
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    S.lib()
+
+    wl = synth.WORKLOADS[args.workload]
+    if args.schatten_p is not None:
+        import dataclasses
+        wl = dataclasses.replace(wl, schatten_p=args.schatten_p)
+    d = synth.make_workload(wl)
+    units = wl.n * wl.K * wl.iters
+    res = {}
+    zs = {}
+    for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        if args.fp32_only and tag == "f64":
+            continue
+        x = torch.from_numpy(d["probs"]).to(device="cuda", dtype=dtype)
+        pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters)
+        ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
+        z = torch.empty_like(x)
+        log(f"[bench] {wl.name} {tag}: warmup {args.warmup}, steps {args.steps}")
+        ms_gpu, ms_wall = time_solves(S, torch, pr, x, z, ws, args.steps, args.warmup)
+        zs[tag] = z.double().cpu().numpy()
+        # per-kernel durations: a second pass over the same steps with HIP events around each launch
+        S.segsalsa_profile_read(reset=True)
+        S.segsalsa_profile_enable(True)
+        for _ in range(args.steps):
+            S.segsalsa_str_solve(pr, x, z, ws)
+        torch.cuda.synchronize()
+        S.segsalsa_profile_enable(False)
+        tot = S.segsalsa_profile_read(reset=True)
+        phases = {name: dict(avg_us=1e3 * tot[name][0] / max(1, tot[name][1]), launches=tot[name][1])
+                  for name in S.PHASES[:4]}
+        res[tag] = dict(ms_per_step=ms_gpu, ms_wall=ms_wall, value=units / (ms_gpu * 1e-3), phases=phases)
+        log(f"[bench] {tag}: {ms_gpu:.3f} ms/step, {units / (ms_gpu * 1e-3):.4g} units/s, phases {phases}")
+        del ws, x, z
+        torch.cuda.empty_cache()
+
+    z_err = float(np.max(np.abs(zs["f32"] - zs["f64"]))) if "f64" in zs else None
+    b = 4
+    prox = res["f32"]["phases"]["prox_rhs"]
+    bytes_launch = wl.n * wl.K * prox_bytes_per_unit(wl.L, b)
+    achieved = bytes_launch / (prox["avg_us"] * 1e-6) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(wl.name, "f32", src_hash)
+    value = res["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["f32"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "H": wl.H, "W": wl.W, "K": wl.K, "patch": f"{2 * wl.M + 1}x{2 * wl.M + 1}",
+                   "schatten_p": wl.schatten_p, "lambda": wl.lam, "mu": wl.mu, "rounds": wl.iters},
+        "roofline": {"bound": "hbm", "kernel": "prox_rhs", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch_alg": bytes_launch,
+                     "avg_launch_us": prox["avg_us"], "kernel_source_hash": src_hash},
+        "z_err_fp32_vs_fp64": z_err,
+        "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in res["f32"]["phases"].items()},
+    }
+    if "f64" in res:
+        out["fp64"] = {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
+                       "phases_us": {k: round(v["avg_us"], 3) for k, v in res["f64"]["phases"].items()}}
+        out["speedup_fp32_vs_fp64"] = res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"]
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, d["probs"], d["weights"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,23 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
                                           const void *d1, const void *d2, const void *d3, const void *d4,
                                           hipStream_t stream);
 
+/*
+ * Instrumentation (not part of the method): per-phase GPU time of the rounds
+ * enqueued by segsalsa_str_solve, measured with HIP events recorded on the
+ * caller's stream immediately before and after each kernel launch.  Off by
+ * default; enabling it adds two event records per launch.
+ *   phases: 0 = fused proximity/multiplier/J^T kernel, 1 = fold + row DFT,
+ *           2 = column DFT / symbol division / inverse column DFT,
+ *           3 = inverse row DFT, 4 = reserved.
+ * segsalsa_profile_read waits for the recorded events, adds their elapsed
+ * times to running per-phase totals, and copies the totals (milliseconds and
+ * launch counts, SEGSALSA_NUM_PHASES entries each, HOST, either may be NULL);
+ * reset != 0 clears the totals afterwards.  Thread-safe.
+ */
+#define SEGSALSA_NUM_PHASES 5
+segsalsa_status segsalsa_profile_enable(int32_t on);
+segsalsa_status segsalsa_profile_read(double *ms, int64_t *launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,59 +67,101 @@ struct Plan {
   int nw, kpw;   // prox workgroup: wavefronts and classes per wavefront
   size_t prox_lds;
   FftPlanDev frow, fcol;
-  int rows_per_block, row_threads;
+  int rows_per_block, row_threads, row_ept;
   size_t row_lds;
-  int cols_per_block, col_threads;
+  int cols_per_block, col_threads, col_ept;
   size_t col_lds;
   // workspace offsets (bytes)
-  size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_phat, off_dm, off_d2, off_acc, off_spec, total;
+  size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_frow, off_fcol, off_phat, off_dm, off_d2, off_acc, off_spec,
+      total;
 };
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Tile grid: widest tiles first (64 columns = one wavefront per row), then
-// shorter/narrower ones until the prox kernel's LDS footprint fits.
+constexpr int kTargetGroups = 256;   // one workgroup per compute unit of an MI355X
+
+TileGeom tile_geom(const Plan& p, int tr, int tc) {
+  TileGeom g;
+  g.H = p.H; g.W = p.W; g.M = p.M;
+  g.ntr = ceil_div(p.H, std::min(tr, p.H));
+  g.ntc = ceil_div(p.W, std::min(tc, p.W));
+  g.TR = ceil_div(p.H, g.ntr);
+  g.TC = ceil_div(p.W, g.ntc);
+  g.ER = g.TR + 2 * p.M + 1;
+  g.EC = g.TC + 2 * p.M + 1;
+  g.steps = ceil_div(g.TR * g.TC, 64);
+  return g;
+}
+
+bool fold_lists_fit(const TileGeom& g) {
+  for (int r = 0; r < g.H; ++r)
+    if (fold_list(g, r, true, nullptr) < 0) return false;
+  for (int c = 0; c < g.W; ++c)
+    if (fold_list(g, c, false, nullptr) < 0) return false;
+  return true;
+}
+
+// Tile grid of the prox kernel.  A workgroup processes one tile in
+// ceil(pixels / 64) steps plus a fixed load/store phase; tiles run in
+// batches of (compute units x resident workgroups).  Among the shapes whose
+// LDS footprint fits, take the one with the fewest batches x (steps + 1),
+// breaking ties by the smaller grown-tile overhead.  SEGSALSA_TILE=RxC forces
+// a shape (tuning runs).
 bool choose_tiles(Plan& p) {
-  static const int cand[][2] = {{8, 64}, {8, 32}, {4, 64}, {4, 32}, {4, 16}, {2, 16}, {2, 8}, {1, 8}, {1, 4}, {1, 2}, {1, 1}};
+  static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+  static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
+  const size_t part = 12 * (size_t)p.nw * 64;
+  auto lds_of = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts; };
+  // resident workgroups per CU allowed by the register budget of the chosen instantiation
+  const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw) / 256);
+  const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
   const char* env = std::getenv("SEGSALSA_TILE");
-  int forced_r = 0, forced_c = 0;
-  if (env && std::sscanf(env, "%dx%d", &forced_r, &forced_c) != 2) forced_r = forced_c = 0;
-  const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
-  for (int ci = -1; ci < ncand; ++ci) {
-    int tr, tc;
-    if (ci < 0) {
-      if (forced_r <= 0 || forced_c <= 0) continue;
-      tr = forced_r;
-      tc = forced_c;
-    } else {
-      tr = cand[ci][0];
-      tc = cand[ci][1];
-    }
-    TileGeom g;
-    g.H = p.H; g.W = p.W; g.M = p.M;
-    g.ntr = ceil_div(p.H, std::min(tr, p.H));
-    g.ntc = ceil_div(p.W, std::min(tc, p.W));
-    g.TR = ceil_div(p.H, g.ntr);
-    g.TC = ceil_div(p.W, g.ntc);
-    g.ER = g.TR + 2 * p.M + 1;
-    g.EC = g.TC + 2 * p.M + 1;
-    g.steps = ceil_div(g.TR * g.TC, 64);
-    const size_t lds = (2 * (size_t)p.K * g.ER * g.EC + 12 * (size_t)p.nw * 64) * p.ts;
-    if (lds <= kLdsBudget) {
+  int fr = 0, fc = 0;
+  if (env && std::sscanf(env, "%dx%d", &fr, &fc) == 2 && fr > 0 && fc > 0) {
+    TileGeom g = tile_geom(p, fr, fc);
+    if (lds_of(g) <= kLdsBudget && fold_lists_fit(g)) {
       p.g = g;
-      p.prox_lds = lds;
+      p.prox_lds = lds_of(g);
       return true;
     }
   }
-  return false;
+  bool have = false;
+  TileGeom best{};
+  double best_cost = 0, best_over = 0;
+  for (int tr : rows) {
+    for (int tc : cols) {
+      TileGeom g = tile_geom(p, tr, tc);
+      const size_t lds = lds_of(g);
+      if (lds > kLdsBudget) continue;
+      const int occ = std::max(1, std::min(occ_regs, (int)(kLdsBudget / lds)));
+      const long long slots = (long long)kTargetGroups * occ;
+      const long long batches = (g.ntiles() + slots - 1) / slots;
+      const double cost = (double)batches * (g.steps + 1);
+      const double over = (double)g.ER * g.EC / ((double)g.TR * g.TC);
+      if (!have || cost < best_cost || (cost == best_cost && over < best_over)) {
+        if (!fold_lists_fit(g)) continue;
+        have = true;
+        best = g;
+        best_cost = cost;
+        best_over = over;
+      }
+    }
+  }
+  if (!have) return false;
+  p.g = best;
+  p.prox_lds = lds_of(best);
+  return true;
 }
 
-int round_threads(long long items) {
-  long long t = (items + kFftEpt - 1) / kFftEpt;
+// Elements per thread (2, 4, 8 or 16) and workgroup size of an LDS FFT
+// workgroup holding `items` complex elements: the fewest elements per thread
+// that keep the workgroup within 1024 threads.
+void fft_threads(long long items, int& ept, int& threads) {
+  ept = 2;
+  while (ept < kFftEptMax && (items + ept - 1) / ept > 1024) ept *= 2;
+  long long t = (items + ept - 1) / ept;
   t = (t + 63) / 64 * 64;
-  if (t < 64) t = 64;
-  if (t > 1024) t = 1024;
-  return (int)t;
+  threads = (int)std::max<long long>(64, std::min<long long>(t, 1024));
 }
 
 segsalsa_status validate(const segsalsa_problem* pr, segsalsa_precision prec) {
@@ -164,7 +207,10 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   p.P = (p.K + 1) / 2;
   // prox workgroup: fewest classes per wavefront whose register budget allows ceil(K/kpw) wavefronts
   p.kpw = 0;
+  int kpw_first = 1;
+  if (const char* ek = std::getenv("SEGSALSA_KPW")) kpw_first = std::atoi(ek);
   for (int kpw : {1, 2, 4}) {
+    if (kpw < kpw_first) continue;
     const int nw = ceil_div(p.K, kpw);
     if (nw <= 16 && nw * 64 <= prox_max_threads_rt(p.fp64, p.M, kpw)) {
       p.kpw = kpw;
@@ -183,15 +229,26 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   const size_t cs = 2 * p.ts;
   p.frow = make_fft_plan(p.W);
   p.fcol = make_fft_plan(p.H);
-  const long long cap = p.fp64 ? 8192 : 16384;   // complex elements per FFT workgroup
-  p.rows_per_block = std::max(1, std::min(p.H, (int)(std::min<long long>(cap, 4096) / p.W)));
-  p.row_threads = round_threads((long long)p.rows_per_block * p.W);
-  p.row_lds = (size_t)p.rows_per_block * p.W * cs;
-  int cb = 1;
-  while (cb < 64 && (long long)(cb * 2) * p.H <= cap && cb * 2 <= p.W) cb *= 2;
-  p.cols_per_block = cb;
-  p.col_threads = round_threads((long long)cb * p.H);
-  p.col_lds = (size_t)cb * p.H * cs;
+  // FFT workgroups: a few hundred elements per workgroup at one or two per
+  // thread for latency hiding, whole rows (columns) plus the twiddle table in
+  // LDS; column blocks of 8+ columns on tall images for coalesced rows.
+  const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
+  {
+    long long rpb = std::max<long long>(1, 512 / p.W);
+    rpb = std::max<long long>(1, std::min<long long>(rpb, p.H));
+    p.rows_per_block = (int)rpb;
+    fft_threads(rpb * p.W, p.row_ept, p.row_threads);
+    p.row_lds = (size_t)(rpb + 1) * p.W * cs;
+  }
+  {
+    int cb = 1;
+    while (cb < 64 && cb * 2 <= p.W && (long long)(cb * 2) * p.H <= cap &&
+           ((long long)(cb * 2) * p.H <= 1024 || cb * 2 <= 8))
+      cb *= 2;
+    p.cols_per_block = cb;
+    fft_threads((long long)cb * p.H, p.col_ept, p.col_threads);
+    p.col_lds = (size_t)(cb + 1) * p.H * cs;
+  }
   // workspace layout
   const size_t nt = (size_t)p.g.ntiles();
   size_t off = 0;
@@ -200,6 +257,8 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   p.off_twH = off; off = align_up(off + (size_t)p.H * cs);
   p.off_sx = off; off = align_up(off + (size_t)p.W * 8);
   p.off_sy = off; off = align_up(off + (size_t)p.H * 8);
+  p.off_frow = off; off = align_up(off + (size_t)p.H * kFoldStride * 4);
+  p.off_fcol = off; off = align_up(off + (size_t)p.W * kFoldStride * 4);
   const size_t per_step = (size_t)p.K * 64 * p.ts;
   p.off_phat = off; off = align_up(off + nt * p.g.steps * per_step);
   p.off_dm = off; off = align_up(off + nt * p.g.steps * per_step * 3);
@@ -207,6 +266,15 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   p.off_acc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts);
   p.off_spec = off; off = align_up(off + (size_t)p.P * p.H * p.W * cs);
   p.total = off;
+  if (const char* lg = std::getenv("SEGSALSA_LOG")) {
+    if (lg[0] == '1')
+      std::fprintf(stderr,
+                   "[segsalsa] plan %s K=%d H=%d W=%d M=%d: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
+                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d; cols/block=%d threads=%d ept=%d; workspace %zu B\n",
+                   p.fp64 ? "fp64" : "fp32", p.K, p.H, p.W, p.M, p.g.ntr, p.g.ntc, p.g.TR, p.g.TC, p.g.ntiles(),
+                   p.g.steps, p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.cols_per_block,
+                   p.col_threads, p.col_ept, p.total);
+  }
   return SEGSALSA_OK;
 }
 
@@ -219,6 +287,55 @@ segsalsa_status check_ws(const Plan& p, const void* ws, size_t bytes) {
   if (bytes < p.total) return fail(SEGSALSA_ERR_WORKSPACE, "workspace %zu bytes < required %zu", bytes, p.total);
   return SEGSALSA_OK;
 }
+
+
+// ---------------------------------------------------------------------------
+// Instrumentation: HIP events recorded on the caller's stream around each
+// launch of a round, accumulated per phase when read back.
+// ---------------------------------------------------------------------------
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double ms[SEGSALSA_NUM_PHASES] = {0};
+  long long count[SEGSALSA_NUM_PHASES] = {0};
+};
+ProfState g_prof;
+
+hipEvent_t prof_event_locked() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseTimer {
+  int phase;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  PhaseTimer(int ph, hipStream_t s) : phase(ph), st(s) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on) return;
+    a = prof_event_locked();
+    if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+  }
+  void stop() {
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t b = prof_event_locked();
+    if (b && hipEventRecord(b, st) == hipSuccess) g_prof.pending.push_back({phase, a, b});
+    a = nullptr;
+  }
+};
 
 template <typename T>
 hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* ws, hipStream_t st) {
@@ -236,7 +353,9 @@ hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* 
   a.tau = pr->lambda / pr->mu;
   a.pkind = pr->schatten_p == 1.0 ? kSchatten1 : (pr->schatten_p == 2.0 ? kSchatten2 : kSchattenInf);
   for (int j = 0; j < p.L; ++j) a.c[j] = (T)pr->patch_weights[j];
+  PhaseTimer t0(0, st);
   hipError_t e = launch_prox(a, p.kpw, p.prox_lds, st);
+  t0.stop();
   if (e != hipSuccess) return e;
 
   RowFwdArgs<T> rf;
@@ -245,10 +364,14 @@ hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* 
   rf.P = p.P;
   rf.rows_per_block = p.rows_per_block;
   rf.acc = a.acc;
+  rf.frow = wsp<int>(ws, p.off_frow);
+  rf.fcol = wsp<int>(ws, p.off_fcol);
   rf.spec = wsp<C2<T>>(ws, p.off_spec);
   rf.tw = wsp<C2<T>>(ws, p.off_twW);
   rf.plan = p.frow;
-  e = launch_rows_fwd(rf, p.row_threads, p.row_lds, st);
+  PhaseTimer t1(1, st);
+  e = launch_rows_fwd(rf, p.row_ept, p.row_threads, p.row_lds, st);
+  t1.stop();
   if (e != hipSuccess) return e;
 
   double wsum = 0.0;
@@ -266,7 +389,9 @@ hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* 
   ca.wsum = wsum;
   ca.scale = 1.0 / ((double)p.H * (double)p.W);
   ca.plan = p.fcol;
-  e = launch_cols(ca, p.col_threads, p.col_lds, st);
+  PhaseTimer t2(2, st);
+  e = launch_cols(ca, p.col_ept, p.col_threads, p.col_lds, st);
+  t2.stop();
   if (e != hipSuccess) return e;
 
   RowInvArgs<T> ri;
@@ -276,7 +401,10 @@ hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* 
   ri.z = z;
   ri.tw = rf.tw;
   ri.plan = p.frow;
-  return launch_rows_inv(ri, p.row_threads, p.row_lds, st);
+  PhaseTimer t3(3, st);
+  e = launch_rows_inv(ri, p.row_ept, p.row_threads, p.row_lds, st);
+  t3.stop();
+  return e;
 }
 
 template <typename T>
@@ -285,6 +413,9 @@ segsalsa_status solve_t(const Plan& p, const segsalsa_problem* pr, const void* i
   T* z = reinterpret_cast<T*>(z_out);
   hipError_t e;
   SetupArgs<T> sa;
+  sa.g = p.g;
+  sa.frow = wsp<int>(ws, p.off_frow);
+  sa.fcol = wsp<int>(ws, p.off_fcol);
   sa.H = p.H; sa.W = p.W;
   sa.twW = wsp<C2<T>>(ws, p.off_twW);
   sa.twH = wsp<C2<T>>(ws, p.off_twH);
@@ -430,6 +561,38 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem* prob, segsalsa
   hipError_t e = p.fp64 ? run_state<double>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream)
                         : run_state<float>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream);
   return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "state import kernel");
+}
+
+segsalsa_status segsalsa_profile_enable(int32_t on) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_profile_read(double* ms, int64_t* launches, int32_t reset) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& pe : g_prof.pending) {
+    float t = 0.0f;
+    hipError_t e = hipEventSynchronize(pe.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, pe.a, pe.b);
+    if (e != hipSuccess) return hip_fail(e, "profile event");
+    g_prof.ms[pe.phase] += t;
+    g_prof.count[pe.phase] += 1;
+    g_prof.pool.push_back(pe.a);
+    g_prof.pool.push_back(pe.b);
+  }
+  g_prof.pending.clear();
+  for (int i = 0; i < SEGSALSA_NUM_PHASES; ++i) {
+    if (ms) ms[i] = g_prof.ms[i];
+    if (launches) launches[i] = g_prof.count[i];
+    if (reset) {
+      g_prof.ms[i] = 0.0;
+      g_prof.count[i] = 0;
+    }
+  }
+  return SEGSALSA_OK;
 }
 
 }  // extern "C"

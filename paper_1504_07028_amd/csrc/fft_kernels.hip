@@ -17,7 +17,8 @@
 //   rows_inv : inverse DFT along rows, unpack into z
 // Each 1-D transform runs in LDS as a mixed-radix Stockham FFT (radix 2, 3,
 // 4, 5, 8 butterflies in registers; any other prime factor as a direct DFT
-// stage).  Twiddles come from exactly rounded tables built once per solve.
+// stage).  Twiddles come from exactly rounded tables built once per solve and
+// are staged in LDS next to the data.
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
 
@@ -125,10 +126,10 @@ struct Bfly<T, 8> {
 // One Stockham stage with a register butterfly of radix R, in place in LDS.
 // nb transforms of length N; element i of transform b sits at b*bs + i*es.
 // Ns is the product of the radices of the previous stages.
-template <typename T, int R>
-__device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* __restrict__ tw, int Ns,
+template <typename T, int R, int EPT>
+__device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* tw, int Ns,
                           bool inv) {
-  constexpr int IT = (kFftEpt + R - 1) / R;
+  constexpr int IT = (EPT + R - 1) / R;
   const T sg = inv ? T(1) : T(-1);
   const int NR = N / R;
   const int total = nb * NR;
@@ -165,16 +166,16 @@ __device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>
 }
 
 // Stockham stage of any radix R as a direct DFT: one output per work item.
-template <typename T>
-__device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* __restrict__ tw,
+template <typename T, int EPT>
+__device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
                               int Ns, bool inv) {
   const int NR = N / R;
   const int total = nb * N;
   const int stw = N / (Ns * R);
-  C2<T> out[kFftEpt];
-  int oi[kFftEpt];
+  C2<T> out[EPT];
+  int oi[EPT];
 #pragma unroll
-  for (int it = 0; it < kFftEpt; ++it) {
+  for (int it = 0; it < EPT; ++it) {
     const int item = threadIdx.x + it * blockDim.x;
     oi[it] = -1;
     if (item < total) {
@@ -200,62 +201,31 @@ __device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, 
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < kFftEpt; ++it)
+  for (int it = 0; it < EPT; ++it)
     if (oi[it] >= 0) buf[oi[it]] = out[it];
   __syncthreads();
 }
 
 // Unnormalised DFT (inv = false: exp(-2 pi i ...); inv = true: exp(+2 pi i ...)).
-template <typename T>
-__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* __restrict__ tw,
-                        bool inv) {
+// The workgroup must hold at least nb * N / EPT threads.
+template <typename T, int EPT>
+__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw, bool inv) {
   int Ns = 1;
   for (int s = 0; s < p.nst; ++s) {
     const int R = p.rad[s];
     switch (R) {
-      case 2: stage_reg<T, 2>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 3: stage_reg<T, 3>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 4: stage_reg<T, 4>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 5: stage_reg<T, 5>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 8: stage_reg<T, 8>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      default: stage_generic<T>(buf, p.N, R, nb, es, bs, tw, Ns, inv); break;
+      case 2: stage_reg<T, 2, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 3: stage_reg<T, 3, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 4: stage_reg<T, 4, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 5: stage_reg<T, 5, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      case 8: stage_reg<T, 8, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
+      default: stage_generic<T, EPT>(buf, p.N, R, nb, es, bs, tw, Ns, inv); break;
     }
     Ns *= R;
   }
 }
 
-// Right-hand side at (k, r, c): the sum over every tile whose grown region
-// covers (r, c) (periodically) of its partial sum there.  A source pixel
-// scatters to rows r_s + [-M, M+1], so only tiles holding source rows in
-// r - M - 1 .. r + M (and likewise columns) can contribute.
-template <typename T>
-__device__ T fold_value(const T* __restrict__ acc, const TileGeom& g, int K, int k, int r, int c) {
-  const int M = g.M;
-  T sum = T(0);
-  for (int d = -M - 1; d <= M; ++d) {
-    const int trr = g.trow(wrap_index(r + d, g.H));
-    bool seen = false;
-    for (int d2 = -M - 1; d2 < d; ++d2) seen |= (g.trow(wrap_index(r + d2, g.H)) == trr);
-    if (seen) continue;
-    const int rr0 = g.r0(trr);
-    const int erlim = g.th(trr) + 2 * M;
-    for (int er = wrap_index(r - rr0 + M, g.H); er <= erlim; er += g.H) {
-      for (int e = -M - 1; e <= M; ++e) {
-        const int tcc = g.tcol(wrap_index(c + e, g.W));
-        bool seenc = false;
-        for (int e2 = -M - 1; e2 < e; ++e2) seenc |= (g.tcol(wrap_index(c + e2, g.W)) == tcc);
-        if (seenc) continue;
-        const int cc0 = g.c0(tcc);
-        const int eclim = g.tw(tcc) + 2 * M;
-        const size_t base = (((size_t)(trr * g.ntc + tcc)) * K + k) * g.ER * g.EC + (size_t)er * g.EC;
-        for (int ec = wrap_index(c - cc0 + M, g.W); ec <= eclim; ec += g.W) sum += acc[base + ec];
-      }
-    }
-  }
-  return sum;
-}
-
-template <typename T>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -265,21 +235,37 @@ __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T> 
   const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
+  C2<T>* tw = buf + a.rows_per_block * W;
+  for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tw[t];
+  // right-hand side = sum of the grown-tile partial sums covering (r, c)
+  const size_t plane = (size_t)a.g.ER * a.g.EC;
+  const bool has1 = k1 < a.K;
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
     const int rr = idx / W, c = idx - rr * W;
-    const int r = row0 + rr;
-    C2<T> v;
-    v.x = fold_value(a.acc, a.g, a.K, k0, r, c);
-    v.y = k1 < a.K ? fold_value(a.acc, a.g, a.K, k1, r, c) : T(0);
-    buf[idx] = v;
+    const int* rl = a.frow + (size_t)(row0 + rr) * kFoldStride;
+    const int* cl = a.fcol + (size_t)c * kFoldStride;
+    const int nr = rl[0], nc = cl[0];
+    T s0 = T(0), s1 = T(0);
+    for (int i = 0; i < nr; ++i) {
+      const int ri = rl[1 + i];
+      const int tr = ri >> 8, er = ri & 255;
+      for (int j = 0; j < nc; ++j) {
+        const int cj = cl[1 + j];
+        const size_t tile = (size_t)tr * a.g.ntc + (cj >> 8);
+        const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & 255);
+        s0 += a.acc[off];
+        if (has1) s1 += a.acc[off + plane];
+      }
+    }
+    buf[idx] = C2<T>{s0, s1};
   }
   __syncthreads();
-  fft_lds(buf, a.plan, nb, 1, W, a.tw, false);
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, false);
   C2<T>* out = a.spec + ((size_t)m * H + row0) * W;
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) out[idx] = buf[idx];
 }
 
-template <typename T>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -290,26 +276,28 @@ __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T> a) {
   const int col0 = (blockIdx.x - m * ncb) * CB;
   const int nb = min(CB, W - col0);
   C2<T>* sp = a.spec + (size_t)m * H * W + col0;
+  C2<T>* tw = buf + CB * H;
+  for (int t = threadIdx.x; t < H; t += blockDim.x) tw[t] = a.tw[t];
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
     buf[idx] = sp[(size_t)y * W + j];
   }
   __syncthreads();
-  fft_lds(buf, a.plan, nb, nb, 1, a.tw, false);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, false);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
-    const double inv = a.scale / (3.0 + a.wsum * (a.sx[col0 + j] + a.sy[y]));
-    buf[idx] = cscale(buf[idx], T(inv));
+    const T inv = T(a.scale) / (T(3) + T(a.wsum) * T(a.sx[col0 + j] + a.sy[y]));
+    buf[idx] = cscale(buf[idx], inv);
   }
   __syncthreads();
-  fft_lds(buf, a.plan, nb, nb, 1, a.tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, true);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
     sp[(size_t)y * W + j] = buf[idx];
   }
 }
 
-template <typename T>
+template <typename T, int EPT>
 __global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
@@ -319,9 +307,11 @@ __global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> 
   const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const C2<T>* in = a.spec + ((size_t)m * H + row0) * W;
+  C2<T>* tw = buf + a.rows_per_block * W;
+  for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tw[t];
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) buf[idx] = in[idx];
   __syncthreads();
-  fft_lds(buf, a.plan, nb, 1, W, a.tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, true);
   const int k0 = 2 * m, k1 = 2 * m + 1;
   T* z0 = a.z + ((size_t)k0 * H + row0) * W;
   T* z1 = a.z + ((size_t)k1 * H + row0) * W;
@@ -335,37 +325,65 @@ __global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> 
 
 template <typename K, typename A>
 static hipError_t launch_fft(K fn, const A& a, int blocks, int threads, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  static bool lds_set = false;  // one static per kernel instantiation; idempotent
+  if (!lds_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+    if (e != hipSuccess) return e;
+    lds_set = true;
+  }
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-template <typename T>
-static int row_blocks(int H, int rpb, int P) { return P * ((H + rpb - 1) / rpb); }
+template <typename T, typename A, typename F2, typename F4, typename F8, typename F16>
+static hipError_t launch_ept(int ept, F2 f2, F4 f4, F8 f8, F16 f16, const A& a, int blocks, int threads, size_t lds,
+                             hipStream_t st) {
+  switch (ept) {
+    case 2: return launch_fft(f2, a, blocks, threads, lds, st);
+    case 4: return launch_fft(f4, a, blocks, threads, lds, st);
+    case 8: return launch_fft(f8, a, blocks, threads, lds, st);
+    case 16: return launch_fft(f16, a, blocks, threads, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
-hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_rows_fwd_kernel<float>, a, row_blocks<float>(a.g.H, a.rows_per_block, a.P), threads, lds, st);
+template <typename T>
+static hipError_t rows_fwd_t(const RowFwdArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  const int blocks = a.P * ((a.g.H + a.rows_per_block - 1) / a.rows_per_block);
+  return launch_ept<T>(ept, fft_rows_fwd_kernel<T, 2>, fft_rows_fwd_kernel<T, 4>, fft_rows_fwd_kernel<T, 8>, fft_rows_fwd_kernel<T, 16>, a,
+                       blocks, threads, lds, st);
 }
-hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_rows_fwd_kernel<double>, a, row_blocks<double>(a.g.H, a.rows_per_block, a.P), threads, lds,
-                    st);
+template <typename T>
+static hipError_t cols_t(const ColArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  const int blocks = a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block);
+  return launch_ept<T>(ept, fft_cols_kernel<T, 2>, fft_cols_kernel<T, 4>, fft_cols_kernel<T, 8>, fft_cols_kernel<T, 16>, a, blocks,
+                       threads, lds, st);
 }
-hipError_t launch_cols(const ColArgs<float>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_cols_kernel<float>, a, a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block), threads,
-                    lds, st);
+template <typename T>
+static hipError_t rows_inv_t(const RowInvArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  const int blocks = a.P * ((a.H + a.rows_per_block - 1) / a.rows_per_block);
+  return launch_ept<T>(ept, fft_rows_inv_kernel<T, 2>, fft_rows_inv_kernel<T, 4>, fft_rows_inv_kernel<T, 8>, fft_rows_inv_kernel<T, 16>, a,
+                       blocks, threads, lds, st);
 }
-hipError_t launch_cols(const ColArgs<double>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_cols_kernel<double>, a, a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block), threads,
-                    lds, st);
+
+hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return rows_fwd_t(a, ept, threads, lds, st);
 }
-hipError_t launch_rows_inv(const RowInvArgs<float>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_rows_inv_kernel<float>, a, row_blocks<float>(a.H, a.rows_per_block, a.P), threads, lds, st);
+hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return rows_fwd_t(a, ept, threads, lds, st);
 }
-hipError_t launch_rows_inv(const RowInvArgs<double>& a, int threads, size_t lds, hipStream_t st) {
-  return launch_fft(fft_rows_inv_kernel<double>, a, row_blocks<double>(a.H, a.rows_per_block, a.P), threads, lds,
-                    st);
+hipError_t launch_cols(const ColArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return cols_t(a, ept, threads, lds, st);
+}
+hipError_t launch_cols(const ColArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return cols_t(a, ept, threads, lds, st);
+}
+hipError_t launch_rows_inv(const RowInvArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return rows_inv_t(a, ept, threads, lds, st);
+}
+hipError_t launch_rows_inv(const RowInvArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
+  return rows_inv_t(a, ept, threads, lds, st);
 }
 
 }  // namespace segsalsa

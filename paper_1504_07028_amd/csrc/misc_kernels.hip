@@ -23,6 +23,15 @@ __global__ void setup_kernel(const SetupArgs<T> a) {
     const double h = sinpi((double)t / (double)a.H);
     a.sy[t] = 4.0 * h * h;
   }
+  // fold lists (the host checked that none overflows)
+  if (t < a.H) {
+    int* o = a.frow + (size_t)t * kFoldStride;
+    o[0] = fold_list(a.g, t, true, o + 1);
+  }
+  if (t < a.W) {
+    int* o = a.fcol + (size_t)t * kFoldStride;
+    o[0] = fold_list(a.g, t, false, o + 1);
+  }
 }
 
 template <typename T>

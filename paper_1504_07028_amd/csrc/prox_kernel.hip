@@ -17,7 +17,8 @@
 // tile accumulates over its tile grown by that margin in LDS; the row FFT
 // pass sums the overlapping grown tiles.  A class's accumulator is written by
 // one wavefront only and, within one instruction, lanes hit distinct
-// addresses, so the LDS adds are free of races and their order is fixed.
+// addresses, so plain LDS read-modify-writes (in program order) are free of
+// races and their summation order is fixed.
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
 
@@ -202,25 +203,63 @@ prox_rhs_kernel(const ProxArgs<T> a) {
         a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
         a.dm[(kb * 3 + 1) * 64 + lane] = d3n;
         a.dm[(kb * 3 + 2) * 64 + lane] = d4n;
-        T* ak = acc + k * plane + (lr + M) * EC + (lc + M);
-        atomicAdd(ak, own);
         C2<T>* d2o = reinterpret_cast<C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
+        // New d2 = u2 - Y = Y (N - I) and the J^T scatter of c_j (u2 + d2).
+        // The h part of offset (dy, dx) lands at (dy, dx + 1) with + and at
+        // (dy, dx) with -, the v part at (dy + 1, dx) with + and at (dy, dx)
+        // with -.  Walking the destinations (da, db) in row-major order, each
+        // one sums its (up to three) terms in registers: the h part of the
+        // previous column and the v part of the previous row are carried.
+        // Neighbouring lanes reach the same address through different
+        // offsets, so the read-modify-writes stay in program order: volatile
+        // keeps the compiler from hoisting a later read above an earlier
+        // write (LDS executes one wavefront's accesses in order).
+        T* ak = acc + k * plane + (lr + M) * EC + (lc + M);
+        T vprev[D + 1];
 #pragma unroll
-        for (int j = 0; j < L; ++j) {
-          const int dy = j / D - M, dx = j % D - M;
-          const T yh = Y[kk][j][0], yv = Y[kk][j][1];
-          const T nh = yh * m11 + yv * m12;  // d2 <- u2 - Y = Y (N - I)
-          const T nv = yh * m12 + yv * m22;
-          C2<T> o;
-          o.x = nh;
-          o.y = nv;
-          d2o[j * 64] = o;
-          const T ah = a.c[j] * (T(2) * nh + yh);  // c_j (u2 + d2): P_j^T then D^T
-          const T av = a.c[j] * (T(2) * nv + yv);
-          T* at = ak + dy * EC + dx;
-          atomicAdd(at, -(ah + av));
-          atomicAdd(at + 1, ah);
-          atomicAdd(at + EC, av);
+        for (int q = 0; q <= D; ++q) vprev[q] = T(0);
+#pragma unroll
+        for (int da = -M; da <= M + 1; ++da) {
+          T hprev = T(0);
+#pragma unroll
+          for (int db = -M; db <= M + 1; ++db) {
+            const bool in0 = da <= M && db <= M;
+            T ah = T(0), av = T(0);
+            if (in0) {
+              const int jj = (da + M) * D + (db + M);
+              const T yh = Y[kk][jj][0], yv = Y[kk][jj][1];
+              const T nh = yh * m11 + yv * m12;
+              const T nv = yh * m12 + yv * m22;
+              C2<T> o;
+              o.x = nh;
+              o.y = nv;
+              d2o[jj * 64] = o;
+              ah = a.c[jj] * (T(2) * nh + yh);
+              av = a.c[jj] * (T(2) * nv + yv);
+            }
+            const bool inh = da <= M && db - 1 >= -M;
+            const bool inv = da - 1 >= -M && db <= M;
+            const bool own_here = da == 0 && db == 0;
+            const int q = db + M;
+            if (in0 || inh || inv || own_here) {
+              T gsum = own_here ? own : T(0);
+              if (in0) gsum -= ah + av;
+              if (inh) gsum += hprev;
+              if (inv) gsum += vprev[q];
+              if constexpr (sizeof(T) == 4 && M <= 3) {
+                volatile __attribute__((address_space(3))) T* at =
+                    (volatile __attribute__((address_space(3))) T*)(ak + da * EC + db);
+                *at = *at + gsum;
+              } else {
+                // FP64: the LDS atomic add is fast and keeps register pressure
+                // down; FP32 9x9 / 11x11 patches: the ordered read-modify-write
+                // does not compile at their register pressure.
+                atomicAdd(ak + da * EC + db, gsum);
+              }
+            }
+            hprev = ah;
+            if (q <= D) vprev[q] = av;
+          }
         }
       }
     }
@@ -239,9 +278,13 @@ prox_rhs_kernel(const ProxArgs<T> a) {
 template <typename T, int M, int KPW>
 static hipError_t launch_prox_t(const ProxArgs<T>& a, size_t lds, hipStream_t st) {
   auto fn = prox_rhs_kernel<T, M, KPW>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  static bool lds_set = false;  // idempotent, so a racing second call is harmless
+  if (!lds_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+    if (e != hipSuccess) return e;
+    lds_set = true;
+  }
   hipLaunchKernelGGL(fn, dim3(a.g.ntiles()), dim3(a.nw * 64), lds, st, a);
   return hipGetLastError();
 }

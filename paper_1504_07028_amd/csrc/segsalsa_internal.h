@@ -26,8 +26,9 @@ constexpr int kMaxM = 5;
 constexpr int kMaxL = (2 * kMaxM + 1) * (2 * kMaxM + 1);
 constexpr int kMaxK = 64;
 constexpr int kMaxSide = 4096;
-constexpr int kFftEpt = 16;        // complex elements per thread in one LDS FFT workgroup
+constexpr int kFftEptMax = 16;     // most complex elements per thread in one LDS FFT workgroup
 constexpr int kMaxRadices = 24;
+constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
 
 template <typename T>
 struct C2 {
@@ -56,6 +57,39 @@ struct TileGeom {
   __host__ __device__ int tcol(int x) const { return (int)((((long long)x + 1) * ntc - 1) / W); }
   __host__ __device__ int ntiles() const { return ntr * ntc; }
 };
+
+// The right-hand side at image row (column) x is the sum of the grown-tile
+// partial sums at every grown position that maps onto x periodically.  A
+// source row r_s scatters to r_s + [-M, M+1], so only tiles holding a source
+// row in x - M - 1 .. x + M contribute.  fold_list writes those positions as
+// tile_row * 256 + e (e = position inside the grown tile) and returns their
+// number, or -1 if there are more than kFoldMax.
+constexpr int kFoldMax = 16;
+constexpr int kFoldStride = kFoldMax + 1;   // [count, entries...] per row / column
+
+__host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, int* out) {
+  const int n = is_row ? g.H : g.W;
+  const int M = g.M;
+  int cnt = 0;
+  for (int d = -M - 1; d <= M; ++d) {
+    const int xs = wrap_index(x + d, n);
+    const int t = is_row ? g.trow(xs) : g.tcol(xs);
+    bool seen = false;
+    for (int d2 = -M - 1; d2 < d; ++d2) {
+      const int xs2 = wrap_index(x + d2, n);
+      seen |= ((is_row ? g.trow(xs2) : g.tcol(xs2)) == t);
+    }
+    if (seen) continue;
+    const int o = is_row ? g.r0(t) : g.c0(t);
+    const int lim = (is_row ? g.th(t) : g.tw(t)) + 2 * M;
+    for (int e = wrap_index(x - o + M, n); e <= lim; e += n) {
+      if (cnt >= kFoldMax) return -1;
+      if (out) out[cnt] = t * 256 + e;
+      ++cnt;
+    }
+  }
+  return cnt;
+}
 
 // Per-pixel arithmetic parameters of one round.
 enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3 };
@@ -87,6 +121,8 @@ struct RowFwdArgs {
   int K, P;
   int rows_per_block;
   const T* __restrict__ acc;    // per-tile partial sums
+  const int* __restrict__ frow; // [H][kFoldStride] fold lists of rows
+  const int* __restrict__ fcol; // [W][kFoldStride] fold lists of columns
   C2<T>* __restrict__ spec;     // [P][H][W]
   const C2<T>* __restrict__ tw; // W twiddles exp(-2 pi i t / W)
   FftPlanDev plan;

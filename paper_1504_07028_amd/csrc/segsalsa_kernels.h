@@ -39,16 +39,19 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
 hipError_t launch_prox(const ProxArgs<float>& a, int kpw, size_t lds, hipStream_t st);
 hipError_t launch_prox(const ProxArgs<double>& a, int kpw, size_t lds, hipStream_t st);
 
-hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<float>& a, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<double>& a, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<float>& a, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<double>& a, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
 
 // Set-up, initialisation and data-movement kernels (misc_kernels.hip).
 template <typename T>
 struct SetupArgs {
+  TileGeom g;
+  int* frow;    // [H][kFoldStride]
+  int* fcol;    // [W][kFoldStride]
   int H, W;
   C2<T>* twW;   // exp(-2 pi i t / W), t < W
   C2<T>* twH;   // exp(-2 pi i t / H), t < H

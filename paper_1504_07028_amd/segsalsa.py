@@ -75,6 +75,10 @@ def lib():
     L.segsalsa_str_state_import.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_size_t, c_void_p,
                                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.segsalsa_str_state_import.restype = c_int32
+    L.segsalsa_profile_enable.argtypes = [c_int32]
+    L.segsalsa_profile_enable.restype = c_int32
+    L.segsalsa_profile_read.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), c_int32]
+    L.segsalsa_profile_read.restype = c_int32
     _lib = L
     return L
 
@@ -184,6 +188,21 @@ def segsalsa_str_state_import(problem: Problem, workspace, p_hat, d1, d2, d3, d4
         ctypes.byref(s), _prec(dtype), _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(),
         _dev_ptr(p_hat, "p_hat", dtype, nel), _dev_ptr(d1, "d1", dtype, nel), _dev_ptr(d2, "d2", dtype, 2 * L * nel),
         _dev_ptr(d3, "d3", dtype, nel), _dev_ptr(d4, "d4", dtype, nel), _stream(stream)))
+
+
+PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "reserved")
+
+
+def segsalsa_profile_enable(on: bool):
+    _check(lib().segsalsa_profile_enable(1 if on else 0))
+
+
+def segsalsa_profile_read(reset: bool = True):
+    """Per-phase totals {phase: (milliseconds, launches)} of the event-timed launches."""
+    ms = (c_double * len(PHASES))()
+    cnt = (ctypes.c_int64 * len(PHASES))()
+    _check(lib().segsalsa_profile_read(ms, cnt, 1 if reset else 0))
+    return {name: (ms[i], int(cnt[i])) for i, name in enumerate(PHASES)}
 
 
 def solve(probs, patch_weights, patch_radius, schatten_p=1.0, lam=1.0, mu=1.0, iters=100, input_is_logits=False,
