@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/segsalsa.h declares, and rejects invalid arguments
+with the documented status before anything is enqueued."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "segsalsa.h")
+
+OK, INVALID, UNSUPPORTED, WORKSPACE = 0, 1, 2, 3
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1504_07028_amd import segsalsa
+    if not os.path.exists(segsalsa.LIB_PATH):
+        from paper_1504_07028_amd.build import build
+        build()
+    segsalsa.lib()
+    return segsalsa
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(segsalsa_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(S):
+    names = declared_functions()
+    assert "segsalsa_str_solve" in names and len(names) >= 8
+    lib = ctypes.CDLL(S.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def base_problem(S, **kw):
+    args = dict(K=4, H=16, W=20, patch_radius=1, patch_weights=[1.0] * 9, schatten_p=1.0, lam=1.0, mu=1.0, iters=5)
+    args.update(kw)
+    return S.Problem(**args)
+
+
+def status_of_size(S, pr, prec=0):
+    n = ctypes.c_size_t(0)
+    s = pr.c_struct()
+    return S.lib().segsalsa_str_workspace_size(ctypes.byref(s), prec, ctypes.byref(n)), n.value
+
+
+def test_workspace_size_grows_with_problem(S):
+    st, small = status_of_size(S, base_problem(S))
+    assert st == OK and small > 0
+    st, big = status_of_size(S, base_problem(S, H=64, W=64))
+    assert st == OK and big > small
+    st, f64 = status_of_size(S, base_problem(S), prec=1)
+    assert st == OK and f64 > small
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(K=1), INVALID), (dict(K=65), UNSUPPORTED), (dict(H=0), INVALID), (dict(W=-3), INVALID),
+    (dict(H=1, W=1), INVALID), (dict(H=5000), UNSUPPORTED), (dict(patch_radius=-1), INVALID),
+    (dict(patch_radius=6, patch_weights=[1.0] * 169), UNSUPPORTED),
+    (dict(patch_weights=[1.0] * 8 + [math.nan]), INVALID), (dict(schatten_p=1.5), UNSUPPORTED),
+    (dict(schatten_p=math.nan), INVALID), (dict(schatten_p=0.5), UNSUPPORTED), (dict(lam=-1.0), INVALID),
+    (dict(lam=math.inf), INVALID), (dict(mu=0.0), INVALID), (dict(mu=-2.0), INVALID), (dict(iters=-1), INVALID),
+    (dict(tol=1e-3), INVALID), (dict(tol=-1.0), INVALID), (dict(residual_every=-1), INVALID),
+])
+def test_invalid_problems(S, kw, code):
+    st, _ = status_of_size(S, base_problem(S, **kw))
+    assert st == code
+    assert S.lib().segsalsa_last_error().decode() != ""
+
+
+def test_bad_precision_and_null_problem(S):
+    n = ctypes.c_size_t(0)
+    assert S.lib().segsalsa_str_workspace_size(None, 0, ctypes.byref(n)) == INVALID
+    s = base_problem(S).c_struct()
+    assert S.lib().segsalsa_str_workspace_size(ctypes.byref(s), 7, ctypes.byref(n)) == INVALID
+
+
+def call_solve(S, pr, inp, z, ws, wsb, prec=0, stats=None):
+    s = pr.c_struct()
+    return S.lib().segsalsa_str_solve(ctypes.byref(s), prec, ctypes.c_void_p(inp), ctypes.c_void_p(z),
+                                      ctypes.c_void_p(ws), wsb, stats, None)
+
+
+def test_solve_argument_errors_before_launch(S):
+    """Errors detected on the host; the fake device addresses are never dereferenced."""
+    pr = base_problem(S)
+    _, need = status_of_size(S, pr)
+    fake_in, fake_z, fake_ws = 0x100000, 0x200000, 0x300000
+    assert call_solve(S, pr, fake_in, None, fake_ws, need) == INVALID           # z_out NULL
+    assert call_solve(S, pr, None, fake_z, fake_ws, need) == INVALID            # input NULL
+    assert call_solve(S, pr, fake_in, fake_in, fake_ws, need) == INVALID        # aliasing
+    assert call_solve(S, pr, fake_in + 2, fake_z, fake_ws, need) == INVALID     # misaligned
+    assert call_solve(S, pr, fake_in, fake_z, None, need) == WORKSPACE          # no workspace
+    assert call_solve(S, pr, fake_in, fake_z, fake_ws + 8, need) == WORKSPACE   # misaligned workspace
+    assert call_solve(S, pr, fake_in, fake_z, fake_ws, need - 1) == WORKSPACE   # too small
+    pr_res = base_problem(S, residual_every=5)
+    assert call_solve(S, pr_res, fake_in, fake_z, fake_ws, need) == INVALID     # residuals need stats
+    assert call_solve(S, base_problem(S, K=1), fake_in, fake_z, fake_ws, need) == INVALID
+
+
+def test_labels_and_state_argument_errors(S):
+    L = S.lib()
+    assert L.segsalsa_str_labels(0, 4, 4, 0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), None) == INVALID
+    assert L.segsalsa_str_labels(3, 4, 4, 0, None, ctypes.c_void_p(0x2000), None) == INVALID
+    pr = base_problem(S)
+    s = pr.c_struct()
+    _, need = status_of_size(S, pr)
+    assert L.segsalsa_str_state_export(ctypes.byref(s), 0, None, need, None, None, None, None, None) == WORKSPACE
+    assert L.segsalsa_str_state_import(ctypes.byref(s), 0, ctypes.c_void_p(0x300000), need, None, None, None, None,
+                                       None, None) == INVALID
+
+
+def test_status_strings(S):
+    L = S.lib()
+    assert L.segsalsa_status_string(0) == b"SEGSALSA_OK"
+    assert L.segsalsa_status_string(3) == b"SEGSALSA_ERR_WORKSPACE"
+
+
+def test_binding_rejects_host_tensors(S):
+    import torch
+    pr = base_problem(S)
+    x = torch.zeros(4, 16, 20, dtype=torch.float32)
+    with pytest.raises(TypeError):
+        S.segsalsa_str_solve(pr, x, x.clone(), torch.zeros(10, dtype=torch.uint8))
+
+
+def test_gpus_flag_rejected():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
