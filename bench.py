@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 512 MiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,6 +126,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     S.lib()
+
+    if args.calibrate_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written")
+        del src, dst
 
     wl = synth.WORKLOADS[args.workload]
     if args.schatten_p is not None:
