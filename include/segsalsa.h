@@ -77,8 +77,10 @@ typedef struct {
   int32_t iters;               /* rounds, >= 0                                                    */
   int32_t input_is_logits;     /* 0: input holds probabilities (>= 0, finite, positive sum per
                                   pixel); 1: input holds logits and p = softmax over classes      */
-  int32_t residual_every;      /* > 0: compute primal/dual residuals every that many rounds and
-                                  report the last ones in stats (needs a HOST stats pointer)     */
+  int32_t residual_every;      /* > 0: compute the primal and dual residuals after every
+                                  residual_every-th round and after the last one, report the last
+                                  ones and the objective in stats (needs a HOST stats pointer);
+                                  each checked round waits for the stream                        */
   double tol;                  /* > 0: stop after the first checked round whose primal and dual
                                   residuals are both <= tol (the paper's stopping rule, Sec. 4);
                                   needs residual_every > 0.  0: run exactly `iters` rounds        */
@@ -91,7 +93,8 @@ typedef struct {
 typedef struct {
   double primal_res;   /* ||G z - u||_F of the last checked round (0 if never checked)        */
   double dual_res;     /* mu ||G (z_new - z_old)||_F of the last checked round                */
-  double objective;    /* eq. (7) at the projection of z onto the simplex, if requested      */
+  double objective;    /* eq. (7) at the projection of z onto the simplex, with the input's
+                          normalised p (computed when residual_every > 0, else 0)            */
   int32_t rounds_done; /* rounds executed by this call                                       */
   int32_t flags;       /* SEGSALSA_FLAG_* bits from the input check of the initialisation    */
 } segsalsa_stats;

@@ -73,7 +73,8 @@ struct Plan {
   size_t col_lds;
   // workspace offsets (bytes)
   size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_frow, off_fcol, off_phat, off_dm, off_d2, off_acc, off_spec,
-      total;
+      off_zprev, off_restile, off_partial, off_out, total;
+  int npartial;
 };
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -111,7 +112,7 @@ bool choose_tiles(Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
   const size_t part = 12 * (size_t)p.nw * 64;
-  auto lds_of = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts; };
+  auto lds_of = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 16; };
   // resident workgroups per CU allowed by the register budget of the chosen instantiation
   const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw) / 256);
   const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
@@ -265,6 +266,12 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   p.off_d2 = off; off = align_up(off + nt * p.g.steps * per_step * 2 * p.L);
   p.off_acc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts);
   p.off_spec = off; off = align_up(off + (size_t)p.P * p.H * p.W * cs);
+  // convergence diagnostics
+  p.off_zprev = off; off = align_up(off + (size_t)p.K * p.H * p.W * p.ts);
+  p.off_restile = off; off = align_up(off + nt * 8);
+  p.npartial = std::max<int>(kDiagBlocks, (int)(((size_t)p.H * p.W + 255) / 256));
+  p.off_partial = off; off = align_up(off + (size_t)p.npartial * 8);
+  p.off_out = off; off = align_up(off + 4 * 8);
   p.total = off;
   if (const char* lg = std::getenv("SEGSALSA_LOG")) {
     if (lg[0] == '1')
@@ -338,7 +345,8 @@ struct PhaseTimer {
 };
 
 template <typename T>
-hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* ws, hipStream_t st) {
+hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* ws, hipStream_t st,
+                         bool residuals = false) {
   ProxArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   a.g = p.g;
@@ -349,6 +357,7 @@ hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* 
   a.dm = wsp<T>(ws, p.off_dm);
   a.d2 = wsp<T>(ws, p.off_d2);
   a.acc = wsp<T>(ws, p.off_acc);
+  a.res_tile = residuals ? wsp<double>(ws, p.off_restile) : nullptr;
   a.mu = pr->mu;
   a.tau = pr->lambda / pr->mu;
   a.pkind = pr->schatten_p == 1.0 ? kSchatten1 : (pr->schatten_p == 2.0 ? kSchatten2 : kSchattenInf);
@@ -437,16 +446,59 @@ segsalsa_status solve_t(const Plan& p, const segsalsa_problem* pr, const void* i
     ia.flags = wsp<int>(ws, p.off_flags);
     if ((e = launch_init(ia, st)) != hipSuccess) return hip_fail(e, "init kernel");
   }
-  for (int it = 0; it < pr->iters; ++it)
-    if ((e = enqueue_round<T>(p, pr, z, ws, st)) != hipSuccess) return hip_fail(e, "round");
+  DiagArgs<T> da;
+  std::memset(&da, 0, sizeof(da));
+  da.g = p.g;
+  da.K = p.K;
+  da.pkind = pr->schatten_p == 1.0 ? kSchatten1 : (pr->schatten_p == 2.0 ? kSchatten2 : kSchattenInf);
+  da.lambda = pr->lambda;
+  for (int j = 0; j < p.L; ++j) {
+    da.cw[j] = (double)(T)pr->patch_weights[j];
+    da.wsum += da.cw[j] * da.cw[j];
+  }
+  da.z = z;
+  da.zprev = wsp<T>(ws, p.off_zprev);
+  da.phat = wsp<T>(ws, p.off_phat);
+  da.partial = wsp<double>(ws, p.off_partial);
+  da.out = wsp<double>(ws, p.off_out);
+  const size_t nel = (size_t)p.K * p.H * p.W;
+  const int every = pr->residual_every;
+  double rp = 0.0, rd = 0.0;
+  int done = 0;
+  for (int it = 0; it < pr->iters; ++it) {
+    const bool checked = every > 0 && ((it + 1) % every == 0 || it + 1 == pr->iters);
+    if (checked && (e = launch_copy(z, da.zprev, nel, st)) != hipSuccess) return hip_fail(e, "copy z");
+    if ((e = enqueue_round<T>(p, pr, z, ws, st, checked)) != hipSuccess) return hip_fail(e, "round");
+    done = it + 1;
+    if (!checked) continue;
+    if ((e = launch_reduce(wsp<double>(ws, p.off_restile), p.g.ntiles(), da.out, 0, st)) != hipSuccess)
+      return hip_fail(e, "residual reduce");
+    if ((e = launch_dual_res(da, st)) != hipSuccess) return hip_fail(e, "dual residual");
+    double host[2];
+    if ((e = hipMemcpyAsync(host, da.out, sizeof(host), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "residual copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "stream sync");
+    rp = std::sqrt(std::max(host[0], 0.0));
+    rd = pr->mu * std::sqrt(std::max(host[1], 0.0));
+    if (pr->tol > 0.0 && rp <= pr->tol && rd <= pr->tol) break;  // stopping rule of Sec. 4
+  }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     int flags = 0;
+    double obj = 0.0;
+    if (every > 0) {
+      if ((e = launch_objective(da, st)) != hipSuccess) return hip_fail(e, "objective");
+      if ((e = hipMemcpyAsync(&obj, da.out + 2, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e, "objective copy");
+    }
     if ((e = hipMemcpyAsync(&flags, wsp<int>(ws, p.off_flags), sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
       return hip_fail(e, "flags copy");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "stream sync");
     stats->flags = flags;
-    stats->rounds_done = pr->iters;
+    stats->rounds_done = done;
+    stats->primal_res = rp;
+    stats->dual_res = rd;
+    stats->objective = obj;
   }
   return SEGSALSA_OK;
 }
@@ -520,7 +572,6 @@ segsalsa_status segsalsa_str_solve(const segsalsa_problem* prob, segsalsa_precis
   if ((prob->residual_every > 0 || prob->tol > 0.0) && !stats)
     return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every / tol need a stats pointer");
   if ((s = check_ws(p, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
-  if (prob->residual_every > 0) return fail(SEGSALSA_ERR_UNSUPPORTED, "residual_every is not available yet");
   return p.fp64 ? solve_t<double>(p, prob, input, z_out, workspace, stats, stream)
                 : solve_t<float>(p, prob, input, z_out, workspace, stats, stream);
 }

@@ -109,7 +109,8 @@ prox_rhs_kernel(const ProxArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
   T* acc = zt + K * plane;             // [K][ER][EC] G^T(u + d) partial sums
-  T* part = acc + K * plane;           // [2][6][nw][64] per-class partial sums
+  // [2][6][nw][64] per-class partial sums, 16-byte aligned (also read as doubles)
+  T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
 
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
@@ -123,6 +124,8 @@ prox_rhs_kernel(const ProxArgs<T> a) {
 
   const int P = th * tw;
   const int nsteps = (P + 63) >> 6;
+  const bool want_res = a.res_tile != nullptr;
+  double rp_acc = 0.0;
   for (int s = 0; s < nsteps; ++s) {
     const int f = (s << 6) + lane;
     const bool valid = f < P;
@@ -131,12 +134,12 @@ prox_rhs_kernel(const ProxArgs<T> a) {
     const size_t stepbase = ((size_t)tile * g.steps + s) * K;
 
     T Y[KPW][L][2];
-    T pk[KPW], v1[KPW], v3[KPW], v4[KPW];
+    T pk[KPW], v1[KPW], v3[KPW], v4[KPW], zcs[KPW];
     T ps = T(0), pq = T(0), psv = T(0), pa = T(0), pb = T(0), pc = T(0);
 #pragma unroll
     for (int kk = 0; kk < KPW; ++kk) {
       const int k = wid + kk * nw;
-      pk[kk] = v1[kk] = v3[kk] = v4[kk] = T(0);
+      pk[kk] = v1[kk] = v3[kk] = v4[kk] = zcs[kk] = T(0);
       if (k < K && valid) {
         const size_t kb = stepbase + k;
         pk[kk] = a.phat[kb * 64 + lane];
@@ -145,6 +148,7 @@ prox_rhs_kernel(const ProxArgs<T> a) {
         const T d4 = a.dm[(kb * 3 + 2) * 64 + lane];
         const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
         const T zc = zk[0];
+        zcs[kk] = zc;
         v1[kk] = zc - d1;
         v3[kk] = zc - d3;
         v4[kk] = zc - d4;
@@ -203,6 +207,12 @@ prox_rhs_kernel(const ProxArgs<T> a) {
         a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
         a.dm[(kb * 3 + 1) * 64 + lane] = d3n;
         a.dm[(kb * 3 + 2) * 64 + lane] = d4n;
+        if (want_res) {  // primal residual: d_new - d_old = u - H z (eq. (14))
+          const double e1 = (double)d1n - (double)(zcs[kk] - v1[kk]);
+          const double e3 = (double)d3n - (double)(zcs[kk] - v3[kk]);
+          const double e4 = (double)d4n - (double)(zcs[kk] - v4[kk]);
+          rp_acc += e1 * e1 + e3 * e3 + e4 * e4;
+        }
         C2<T>* d2o = reinterpret_cast<C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
         // New d2 = u2 - Y = Y (N - I) and the J^T scatter of c_j (u2 + d2).
         // The h part of offset (dy, dx) lands at (dy, dx + 1) with + and at
@@ -234,6 +244,12 @@ prox_rhs_kernel(const ProxArgs<T> a) {
               o.x = nh;
               o.y = nv;
               d2o[jj * 64] = o;
+              if (want_res) {  // old d2 = c_j grad z - Y, rebuilt from the LDS tile
+                const T* zr = zt + k * plane + (lr + M + da) * EC + (lc + M + db);
+                const double oh = (double)(a.c[jj] * (zr[1] - zr[0]) - yh);
+                const double ov = (double)(a.c[jj] * (zr[EC] - zr[0]) - yv);
+                rp_acc += ((double)nh - oh) * ((double)nh - oh) + ((double)nv - ov) * ((double)nv - ov);
+              }
               ah = a.c[jj] * (T(2) * nh + yh);
               av = a.c[jj] * (T(2) * nv + yv);
             }
@@ -266,6 +282,18 @@ prox_rhs_kernel(const ProxArgs<T> a) {
     }  // valid
   }
   __syncthreads();
+  if (want_res) {  // fixed-order reduction of the tile's primal-residual partial sums
+    double v = rp_acc;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    double* red = reinterpret_cast<double*>(part);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < nw; ++w) t += red[w];
+      a.res_tile[tile] = t;
+    }
+  }
   T* blk = a.acc + (size_t)tile * K * g.ER * g.EC;
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;

@@ -104,6 +104,7 @@ struct ProxArgs {
   T* __restrict__ dm;
   T* __restrict__ d2;
   T* __restrict__ acc;
+  double* __restrict__ res_tile;  // non-null on checked rounds: per-tile sum of (d_new - d_old)^2
   double mu, tau;
   int pkind;
   T c[kMaxL];

@@ -89,6 +89,29 @@ struct StateArgs {
 hipError_t launch_state(const StateArgs<float>& a, hipStream_t st);
 hipError_t launch_state(const StateArgs<double>& a, hipStream_t st);
 
+// Convergence diagnostics (residual_kernels.hip).
+constexpr int kDiagBlocks = 1024;
+template <typename T>
+struct DiagArgs {
+  TileGeom g;
+  int K;
+  int pkind;
+  double lambda, wsum;
+  const T* z;        // [K][H][W] current z
+  T* zprev;          // [K][H][W] z before the round; scratch for the projection in the objective
+  const T* phat;     // tile layout
+  double* partial;   // per-block partial sums
+  double* out;       // [0] primal^2, [1] dual^2 / mu^2, [2] objective
+  double cw[kMaxL];  // multipliers c_j
+};
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t st);
+hipError_t launch_copy(const double* src, double* dst, size_t n, hipStream_t st);
+hipError_t launch_dual_res(const DiagArgs<float>& a, hipStream_t st);
+hipError_t launch_dual_res(const DiagArgs<double>& a, hipStream_t st);
+hipError_t launch_objective(const DiagArgs<float>& a, hipStream_t st);
+hipError_t launch_objective(const DiagArgs<double>& a, hipStream_t st);
+hipError_t launch_reduce(const double* partial, int count, double* out, int slot, hipStream_t st);
+
 hipError_t launch_labels(int K, int H, int W, const float* z, int32_t* labels, hipStream_t st);
 hipError_t launch_labels(int K, int H, int W, const double* z, int32_t* labels, hipStream_t st);
 

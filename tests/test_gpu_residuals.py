@@ -1,0 +1,68 @@
+"""GPU residuals, objective and the residual-threshold stopping rule (Sec. 4) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import need_gpu, problem_inputs, say
+from oracle import segsalsa_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+def solve_stats(S, probs, c, M, p, lam, mu, iters, dtype, every, tol=0.0):
+    K, H, W = probs.shape
+    x = torch.from_numpy(probs).to(device="cuda", dtype=dtype)
+    pr = S.Problem(K, H, W, M, c, p, lam, mu, iters, residual_every=every, tol=tol)
+    ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
+    z = torch.empty_like(x)
+    st = S.segsalsa_str_solve(pr, x, z, ws, stats=True)
+    return z, st
+
+
+def oracle_residual_history(probs, c, M, p, lam, mu, iters, every):
+    pr = R.Problem(np.asarray(c, dtype=np.float64), M, p, lam, mu)
+    ph = probs / probs.sum(0)
+    st = R.init_state(ph, (2 * M + 1) ** 2)
+    hist = []
+    for it in range(iters):
+        st, rp, rd = R.salsa_round(st, ph, pr, want_residuals=True)
+        if (it + 1) % every == 0 or it + 1 == iters:
+            hist.append((it + 1, rp, rd))
+    return st, ph, pr, hist
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0, math.inf])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_residuals_and_objective_match_oracle(p, dtype):
+    S = need_gpu()
+    H, W, K, M, iters = 23, 31, 5, 2, 10
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=12)
+    z, st = solve_stats(S, probs, c, M, p, 0.7, 1.2, iters, dtype, every=4)
+    ost, ph, pr, hist = oracle_residual_history(probs, c, M, p, 0.7, 1.2, iters, 4)
+    _, rp, rd = hist[-1]
+    obj = R.objective(ost.z, ph, pr)
+    tol = 1e-9 if dtype == torch.float64 else 2e-4
+    say(f"  gpu rp {st['primal_res']:.6e} rd {st['dual_res']:.6e} obj {st['objective']:.10f}")
+    say(f"  ora rp {rp:.6e} rd {rd:.6e} obj {obj:.10f}")
+    assert st["rounds_done"] == iters
+    assert abs(st["primal_res"] - rp) <= tol * max(1.0, rp)
+    assert abs(st["dual_res"] - rd) <= tol * max(1.0, rd)
+    assert abs(st["objective"] - obj) <= tol * abs(obj)
+
+
+def test_stopping_rule_stops_where_the_oracle_does():
+    S = need_gpu()
+    H, W, K, M = 16, 18, 3, 1
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=13)
+    every, iters, tol = 5, 600, 1e-2
+    z, st = solve_stats(S, probs, c, M, 1.0, 0.5, 2.0, iters, torch.float64, every, tol)
+    _, _, _, hist = oracle_residual_history(probs, c, M, 1.0, 0.5, 2.0, iters, every)
+    first = next((r for r, rp, rd in hist if rp <= tol and rd <= tol), iters)
+    say(f"  gpu stopped after {st['rounds_done']} rounds, oracle after {first}")
+    assert st["rounds_done"] == first < iters
+    assert st["primal_res"] <= tol and st["dual_res"] <= tol
+    # the stopped run equals a fixed-round run of the same length, bit for bit
+    z2, _ = solve_stats(S, probs, c, M, 1.0, 0.5, 2.0, st["rounds_done"], torch.float64, 0)
+    assert torch.equal(z, z2)
