@@ -87,6 +87,11 @@ typedef struct {
   int32_t warm_start;          /* 0: initialise the state from the input.  1: continue from the
                                   state already in the workspace and z_out, left there by an
                                   earlier call with the same problem, precision and workspace     */
+  int32_t use_graph;           /* 1: capture the whole solve (set-up, initialisation, all rounds)
+                                  into a hipGraph on first use and replay it on later calls with
+                                  the same problem, buffers and workspace (one graph launch per
+                                  call; cannot be combined with residual_every).  0: launch the
+                                  kernels directly                                               */
 } segsalsa_problem;
 
 /* Results reported to a HOST stats pointer. */
@@ -132,6 +137,52 @@ segsalsa_status segsalsa_str_workspace_size(const segsalsa_problem *prob, segsal
 segsalsa_status segsalsa_str_solve(const segsalsa_problem *prob, segsalsa_precision precision,
                                    const void *input, void *z_out, void *workspace, size_t workspace_bytes,
                                    segsalsa_stats *stats, hipStream_t stream);
+
+/* One image of a batch: shape, SALSA parameters, and element offsets of its
+ * [K][H][W] input and output inside the packed batch buffers. */
+typedef struct {
+  int32_t K, H, W;        /* as in segsalsa_problem                                       */
+  int64_t in_offset;      /* first element of the image in input_packed (>= 0)             */
+  int64_t out_offset;     /* first element of the image in z_packed (>= 0); output ranges
+                             must not overlap                                              */
+  double lambda, mu;      /* prior weight (>= 0) and SALSA penalty (> 0) of this image     */
+} segsalsa_image;
+
+/* Parameters shared by all images of a batch (same meaning as in segsalsa_problem). */
+typedef struct {
+  int32_t patch_radius;
+  const double *patch_weights;   /* HOST, L multipliers c_j                               */
+  double schatten_p;
+  int32_t iters;
+  int32_t input_is_logits;
+  int32_t residual_every;        /* with tol > 0 each image stops on its own: an image whose
+                                    residuals are <= tol leaves the later launches           */
+  double tol;
+  int32_t warm_start;
+  int32_t use_graph;
+} segsalsa_batch_params;
+
+/* Workspace bytes of segsalsa_str_solve_batch for these images (HOST arrays). */
+segsalsa_status segsalsa_str_batch_workspace_size(int32_t n_images, const segsalsa_image *images,
+                                                  const segsalsa_batch_params *params,
+                                                  segsalsa_precision precision, size_t *bytes /* HOST, out */);
+
+/*
+ * SegSALSA-STR on many images of different sizes and class counts at once
+ * (the rounds of Sec. 4 on each image).  Every round is one launch per
+ * kernel for the whole batch (the proximity kernel: one launch per distinct
+ * workgroup shape), so small images share the GPU.
+ *
+ *   images         HOST, n_images descriptors.
+ *   input_packed   device buffer holding every image's input at its in_offset.
+ *   z_packed       device buffer receiving every image's z at its out_offset.
+ *   stats          HOST, n_images entries or NULL (required with residuals).
+ * The result of each image equals segsalsa_str_solve on that image alone.
+ */
+segsalsa_status segsalsa_str_solve_batch(int32_t n_images, const segsalsa_image *images,
+                                         const segsalsa_batch_params *params, segsalsa_precision precision,
+                                         const void *input_packed, void *z_packed, void *workspace,
+                                         size_t workspace_bytes, segsalsa_stats *stats, hipStream_t stream);
 
 /*
  * Labels y_i = argmax_k z_ki, lowest k on ties (the segmentation read out of

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -165,54 +166,93 @@ void fft_threads(long long items, int& ept, int& threads) {
   threads = (int)std::max<long long>(64, std::min<long long>(t, 1024));
 }
 
-segsalsa_status validate(const segsalsa_problem* pr, segsalsa_precision prec) {
-  if (!pr) return fail(SEGSALSA_ERR_INVALID_ARG, "problem is NULL");
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+
+// Parameters shared by every image of a solve.
+struct Common {
+  bool fp64;
+  size_t ts;
+  int M, L, pkind;
+  double w[kMaxL];
+  double p;
+  int iters, logits, every, warm, graph;
+  double tol;
+};
+
+segsalsa_status validate_common(int M, const double* weights, double p, int iters, int logits, int every, double tol,
+                                int warm, int graph, segsalsa_precision prec, Common& c) {
   if (prec != SEGSALSA_FP32 && prec != SEGSALSA_FP64) return fail(SEGSALSA_ERR_INVALID_ARG, "bad precision %d", (int)prec);
-  if (pr->K < 2) return fail(SEGSALSA_ERR_INVALID_ARG, "K = %d must be >= 2", pr->K);
-  if (pr->K > kMaxK) return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d exceeds %d", pr->K, kMaxK);
-  if (pr->H < 1 || pr->W < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "H = %d, W = %d must be >= 1", pr->H, pr->W);
-  if ((long long)pr->H * pr->W < 2) return fail(SEGSALSA_ERR_INVALID_ARG, "image must have >= 2 pixels");
-  if (pr->H > kMaxSide || pr->W > kMaxSide)
-    return fail(SEGSALSA_ERR_UNSUPPORTED, "H = %d, W = %d exceed %d", pr->H, pr->W, kMaxSide);
-  if (pr->patch_radius < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_radius = %d < 0", pr->patch_radius);
-  if (pr->patch_radius > kMaxM) return fail(SEGSALSA_ERR_UNSUPPORTED, "patch_radius = %d > %d", pr->patch_radius, kMaxM);
-  if (!pr->patch_weights) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_weights is NULL");
-  const int L = (2 * pr->patch_radius + 1) * (2 * pr->patch_radius + 1);
+  if (M < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_radius = %d < 0", M);
+  if (M > kMaxM) return fail(SEGSALSA_ERR_UNSUPPORTED, "patch_radius = %d > %d", M, kMaxM);
+  if (!weights) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_weights is NULL");
+  const int L = (2 * M + 1) * (2 * M + 1);
   for (int j = 0; j < L; ++j)
-    if (!std::isfinite(pr->patch_weights[j])) return fail(SEGSALSA_ERR_INVALID_ARG, "patch weight %d not finite", j);
-  const double p = pr->schatten_p;
+    if (!std::isfinite(weights[j])) return fail(SEGSALSA_ERR_INVALID_ARG, "patch weight %d not finite", j);
   if (std::isnan(p)) return fail(SEGSALSA_ERR_INVALID_ARG, "schatten_p is NaN");
   if (!(p == 1.0 || p == 2.0 || (std::isinf(p) && p > 0)))
     return fail(SEGSALSA_ERR_UNSUPPORTED, "schatten_p = %g (supported: 1, 2, inf)", p);
-  if (!std::isfinite(pr->lambda) || pr->lambda < 0.0) return fail(SEGSALSA_ERR_INVALID_ARG, "lambda = %g", pr->lambda);
-  if (!std::isfinite(pr->mu) || !(pr->mu > 0.0)) return fail(SEGSALSA_ERR_INVALID_ARG, "mu = %g", pr->mu);
-  if (pr->iters < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "iters = %d < 0", pr->iters);
-  if (pr->input_is_logits != 0 && pr->input_is_logits != 1)
-    return fail(SEGSALSA_ERR_INVALID_ARG, "input_is_logits = %d", pr->input_is_logits);
-  if (pr->residual_every < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every = %d", pr->residual_every);
-  if (!std::isfinite(pr->tol) || pr->tol < 0.0) return fail(SEGSALSA_ERR_INVALID_ARG, "tol = %g", pr->tol);
-  if (pr->tol > 0.0 && pr->residual_every == 0)
-    return fail(SEGSALSA_ERR_INVALID_ARG, "tol > 0 needs residual_every > 0");
-  if (pr->warm_start != 0 && pr->warm_start != 1)
-    return fail(SEGSALSA_ERR_INVALID_ARG, "warm_start = %d", pr->warm_start);
+  if (iters < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "iters = %d < 0", iters);
+  if (logits != 0 && logits != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "input_is_logits = %d", logits);
+  if (every < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every = %d", every);
+  if (!std::isfinite(tol) || tol < 0.0) return fail(SEGSALSA_ERR_INVALID_ARG, "tol = %g", tol);
+  if (tol > 0.0 && every == 0) return fail(SEGSALSA_ERR_INVALID_ARG, "tol > 0 needs residual_every > 0");
+  if (warm != 0 && warm != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "warm_start = %d", warm);
+  if (graph != 0 && graph != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "use_graph = %d", graph);
+  if (graph && every > 0) return fail(SEGSALSA_ERR_INVALID_ARG, "use_graph cannot be combined with residual_every");
+  c.fp64 = prec == SEGSALSA_FP64;
+  c.ts = c.fp64 ? 8 : 4;
+  c.M = M;
+  c.L = L;
+  c.pkind = p == 1.0 ? kSchatten1 : (p == 2.0 ? kSchatten2 : kSchattenInf);
+  for (int j = 0; j < L; ++j) c.w[j] = weights[j];
+  c.p = p;
+  c.iters = iters;
+  c.logits = logits;
+  c.every = every;
+  c.tol = tol;
+  c.warm = warm;
+  c.graph = graph;
   return SEGSALSA_OK;
 }
 
-segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, Plan& p) {
-  segsalsa_status s = validate(pr, prec);
+segsalsa_status validate_image(int K, int H, int W, double lambda, double mu) {
+  if (K < 2) return fail(SEGSALSA_ERR_INVALID_ARG, "K = %d must be >= 2", K);
+  if (K > kMaxK) return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d exceeds %d", K, kMaxK);
+  if (H < 1 || W < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "H = %d, W = %d must be >= 1", H, W);
+  if ((long long)H * W < 2) return fail(SEGSALSA_ERR_INVALID_ARG, "image must have >= 2 pixels");
+  if (H > kMaxSide || W > kMaxSide) return fail(SEGSALSA_ERR_UNSUPPORTED, "H = %d, W = %d exceed %d", H, W, kMaxSide);
+  if (!std::isfinite(lambda) || lambda < 0.0) return fail(SEGSALSA_ERR_INVALID_ARG, "lambda = %g", lambda);
+  if (!std::isfinite(mu) || !(mu > 0.0)) return fail(SEGSALSA_ERR_INVALID_ARG, "mu = %g", mu);
+  return SEGSALSA_OK;
+}
+
+segsalsa_status validate_problem(const segsalsa_problem* pr, segsalsa_precision prec, Common& c) {
+  if (!pr) return fail(SEGSALSA_ERR_INVALID_ARG, "problem is NULL");
+  segsalsa_status s = validate_image(pr->K, pr->H, pr->W, pr->lambda, pr->mu);
   if (s != SEGSALSA_OK) return s;
-  p.fp64 = prec == SEGSALSA_FP64;
-  p.ts = p.fp64 ? 8 : 4;
-  p.K = pr->K; p.H = pr->H; p.W = pr->W; p.M = pr->patch_radius;
-  p.L = (2 * p.M + 1) * (2 * p.M + 1);
-  p.P = (p.K + 1) / 2;
+  return validate_common(pr->patch_radius, pr->patch_weights, pr->schatten_p, pr->iters, pr->input_is_logits,
+                         pr->residual_every, pr->tol, pr->warm_start, pr->use_graph, prec, c);
+}
+
+// ---------------------------------------------------------------------------
+// Per-image plan: tile grid, FFT factorisations and launch shapes, and the
+// layout of the image's region of the workspace (offsets from its base).
+// ---------------------------------------------------------------------------
+segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
+  p.fp64 = c.fp64;
+  p.ts = c.ts;
+  p.K = K; p.H = H; p.W = W; p.M = c.M;
+  p.L = c.L;
+  p.P = (K + 1) / 2;
   // prox workgroup: fewest classes per wavefront whose register budget allows ceil(K/kpw) wavefronts
   p.kpw = 0;
   int kpw_first = 1;
   if (const char* ek = std::getenv("SEGSALSA_KPW")) kpw_first = std::atoi(ek);
   for (int kpw : {1, 2, 4}) {
     if (kpw < kpw_first) continue;
-    const int nw = ceil_div(p.K, kpw);
+    const int nw = ceil_div(K, kpw);
     if (nw <= 16 && nw * 64 <= prox_max_threads_rt(p.fp64, p.M, kpw)) {
       p.kpw = kpw;
       p.nw = nw;
@@ -221,55 +261,51 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
   }
   if (p.kpw == 0) {
     p.kpw = 4;
-    p.nw = ceil_div(p.K, 4);
+    p.nw = ceil_div(K, 4);
     if (p.nw * 64 > prox_max_threads_rt(p.fp64, p.M, 4))
-      return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d do not fit one workgroup", p.K, p.M);
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d do not fit one workgroup", K, p.M);
   }
-  if (!choose_tiles(p)) return fail(SEGSALSA_ERR_UNSUPPORTED, "no tile shape fits LDS for K = %d, M = %d", p.K, p.M);
-  // FFT passes
+  if (!choose_tiles(p)) return fail(SEGSALSA_ERR_UNSUPPORTED, "no tile shape fits LDS for K = %d, M = %d", K, p.M);
   const size_t cs = 2 * p.ts;
-  p.frow = make_fft_plan(p.W);
-  p.fcol = make_fft_plan(p.H);
+  p.frow = make_fft_plan(W);
+  p.fcol = make_fft_plan(H);
   // FFT workgroups: a few hundred elements per workgroup at one or two per
   // thread for latency hiding, whole rows (columns) plus the twiddle table in
   // LDS; column blocks of 8+ columns on tall images for coalesced rows.
   const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
   {
-    long long rpb = std::max<long long>(1, 512 / p.W);
-    rpb = std::max<long long>(1, std::min<long long>(rpb, p.H));
+    long long rpb = std::max<long long>(1, 512 / W);
+    rpb = std::max<long long>(1, std::min<long long>(rpb, H));
     p.rows_per_block = (int)rpb;
-    fft_threads(rpb * p.W, p.row_ept, p.row_threads);
-    p.row_lds = (size_t)(rpb + 1) * p.W * cs;
+    fft_threads(rpb * W, p.row_ept, p.row_threads);
+    p.row_lds = (size_t)(rpb + 1) * W * cs;
   }
   {
     int cb = 1;
-    while (cb < 64 && cb * 2 <= p.W && (long long)(cb * 2) * p.H <= cap &&
-           ((long long)(cb * 2) * p.H <= 1024 || cb * 2 <= 8))
+    while (cb < 64 && cb * 2 <= W && (long long)(cb * 2) * H <= cap && ((long long)(cb * 2) * H <= 1024 || cb * 2 <= 8))
       cb *= 2;
     p.cols_per_block = cb;
-    fft_threads((long long)cb * p.H, p.col_ept, p.col_threads);
-    p.col_lds = (size_t)(cb + 1) * p.H * cs;
+    fft_threads((long long)cb * H, p.col_ept, p.col_threads);
+    p.col_lds = (size_t)(cb + 1) * H * cs;
   }
-  // workspace layout
   const size_t nt = (size_t)p.g.ntiles();
   size_t off = 0;
   p.off_flags = off; off = align_up(off + 64);
-  p.off_twW = off; off = align_up(off + (size_t)p.W * cs);
-  p.off_twH = off; off = align_up(off + (size_t)p.H * cs);
-  p.off_sx = off; off = align_up(off + (size_t)p.W * 8);
-  p.off_sy = off; off = align_up(off + (size_t)p.H * 8);
-  p.off_frow = off; off = align_up(off + (size_t)p.H * kFoldStride * 4);
-  p.off_fcol = off; off = align_up(off + (size_t)p.W * kFoldStride * 4);
-  const size_t per_step = (size_t)p.K * 64 * p.ts;
+  p.off_twW = off; off = align_up(off + (size_t)W * cs);
+  p.off_twH = off; off = align_up(off + (size_t)H * cs);
+  p.off_sx = off; off = align_up(off + (size_t)W * 8);
+  p.off_sy = off; off = align_up(off + (size_t)H * 8);
+  p.off_frow = off; off = align_up(off + (size_t)H * kFoldStride * 4);
+  p.off_fcol = off; off = align_up(off + (size_t)W * kFoldStride * 4);
+  const size_t per_step = (size_t)K * 64 * p.ts;
   p.off_phat = off; off = align_up(off + nt * p.g.steps * per_step);
   p.off_dm = off; off = align_up(off + nt * p.g.steps * per_step * 3);
   p.off_d2 = off; off = align_up(off + nt * p.g.steps * per_step * 2 * p.L);
-  p.off_acc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts);
-  p.off_spec = off; off = align_up(off + (size_t)p.P * p.H * p.W * cs);
-  // convergence diagnostics
-  p.off_zprev = off; off = align_up(off + (size_t)p.K * p.H * p.W * p.ts);
+  p.off_acc = off; off = align_up(off + nt * (size_t)K * p.g.ER * p.g.EC * p.ts);
+  p.off_spec = off; off = align_up(off + (size_t)p.P * H * W * cs);
+  p.off_zprev = off; off = align_up(off + (size_t)K * H * W * p.ts);
   p.off_restile = off; off = align_up(off + nt * 8);
-  p.npartial = std::max<int>(kDiagBlocks, (int)(((size_t)p.H * p.W + 255) / 256));
+  p.npartial = std::max<int>(kDiagBlocks, (int)(((size_t)H * W + 255) / 256));
   p.off_partial = off; off = align_up(off + (size_t)p.npartial * 8);
   p.off_out = off; off = align_up(off + 4 * 8);
   p.total = off;
@@ -277,9 +313,9 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
     if (lg[0] == '1')
       std::fprintf(stderr,
                    "[segsalsa] plan %s K=%d H=%d W=%d M=%d: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
-                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d; cols/block=%d threads=%d ept=%d; workspace %zu B\n",
-                   p.fp64 ? "fp64" : "fp32", p.K, p.H, p.W, p.M, p.g.ntr, p.g.ntc, p.g.TR, p.g.TC, p.g.ntiles(),
-                   p.g.steps, p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.cols_per_block,
+                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d; cols/block=%d threads=%d ept=%d; region %zu B\n",
+                   p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.g.ntr, p.g.ntc, p.g.TR, p.g.TC, p.g.ntiles(), p.g.steps,
+                   p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.cols_per_block,
                    p.col_threads, p.col_ept, p.total);
   }
   return SEGSALSA_OK;
@@ -288,13 +324,12 @@ segsalsa_status make_plan(const segsalsa_problem* pr, segsalsa_precision prec, P
 template <typename T>
 T* wsp(void* ws, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off); }
 
-segsalsa_status check_ws(const Plan& p, const void* ws, size_t bytes) {
+segsalsa_status check_ws(size_t need, const void* ws, size_t bytes) {
   if (!ws) return fail(SEGSALSA_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(SEGSALSA_ERR_WORKSPACE, "workspace not 256-byte aligned");
-  if (bytes < p.total) return fail(SEGSALSA_ERR_WORKSPACE, "workspace %zu bytes < required %zu", bytes, p.total);
+  if (bytes < need) return fail(SEGSALSA_ERR_WORKSPACE, "workspace %zu bytes < required %zu", bytes, need);
   return SEGSALSA_OK;
 }
-
 
 // ---------------------------------------------------------------------------
 // Instrumentation: HIP events recorded on the caller's stream around each
@@ -332,6 +367,8 @@ struct PhaseTimer {
   PhaseTimer(int ph, hipStream_t s) : phase(ph), st(s) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     if (!g_prof.on) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     a = prof_event_locked();
     if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
   }
@@ -344,175 +381,510 @@ struct PhaseTimer {
   }
 };
 
-template <typename T>
-hipError_t enqueue_round(const Plan& p, const segsalsa_problem* pr, T* z, void* ws, hipStream_t st,
-                         bool residuals = false) {
-  ProxArgs<T> a;
-  std::memset(&a, 0, sizeof(a));
-  a.g = p.g;
-  a.K = p.K;
-  a.nw = p.nw;
-  a.z = z;
-  a.phat = wsp<T>(ws, p.off_phat);
-  a.dm = wsp<T>(ws, p.off_dm);
-  a.d2 = wsp<T>(ws, p.off_d2);
-  a.acc = wsp<T>(ws, p.off_acc);
-  a.res_tile = residuals ? wsp<double>(ws, p.off_restile) : nullptr;
-  a.mu = pr->mu;
-  a.tau = pr->lambda / pr->mu;
-  a.pkind = pr->schatten_p == 1.0 ? kSchatten1 : (pr->schatten_p == 2.0 ? kSchatten2 : kSchattenInf);
-  for (int j = 0; j < p.L; ++j) a.c[j] = (T)pr->patch_weights[j];
-  PhaseTimer t0(0, st);
-  hipError_t e = launch_prox(a, p.kpw, p.prox_lds, st);
-  t0.stop();
-  if (e != hipSuccess) return e;
 
-  RowFwdArgs<T> rf;
-  rf.g = p.g;
-  rf.K = p.K;
-  rf.P = p.P;
-  rf.rows_per_block = p.rows_per_block;
-  rf.acc = a.acc;
-  rf.frow = wsp<int>(ws, p.off_frow);
-  rf.fcol = wsp<int>(ws, p.off_fcol);
-  rf.spec = wsp<C2<T>>(ws, p.off_spec);
-  rf.tw = wsp<C2<T>>(ws, p.off_twW);
-  rf.plan = p.frow;
+// ---------------------------------------------------------------------------
+// Batch: image regions one after another, then the descriptor tables.
+// ---------------------------------------------------------------------------
+struct ImgRun {
+  Plan plan;
+  size_t base;        // offset of the image's workspace region
+  double lambda, mu;
+  size_t in_off, out_off;   // element offsets into the packed input / output
+};
+
+struct Batch {
+  Common c;
+  std::vector<ImgRun> im;
+  size_t off_tab[5];   // prox, prox with residuals, row DFT, column solve, inverse row DFT
+  size_t total;
+};
+
+template <typename T>
+size_t desc_size(int which) {
+  switch (which) {
+    case 0:
+    case 1: return sizeof(ProxArgs<T>);
+    case 2: return sizeof(RowFwdArgs<T>);
+    case 3: return sizeof(ColArgs<T>);
+    default: return sizeof(RowInvArgs<T>);
+  }
+}
+
+segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, const double* lam, const double* mu,
+                           const Common& c, Batch& b) {
+  b.c = c;
+  b.im.resize(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    segsalsa_status s = validate_image(K[i], H[i], W[i], lam[i], mu[i]);
+    if (s != SEGSALSA_OK) return fail(s, "image %d: %s", i, segsalsa_last_error());
+    s = make_image_plan(K[i], H[i], W[i], c, b.im[i].plan);
+    if (s != SEGSALSA_OK) return s;
+    b.im[i].base = off;
+    b.im[i].lambda = lam[i];
+    b.im[i].mu = mu[i];
+    off = align_up(off + b.im[i].plan.total);
+  }
+  for (int t = 0; t < 5; ++t) {
+    b.off_tab[t] = off;
+    off = align_up(off + (size_t)n * (c.fp64 ? desc_size<double>(t) : desc_size<float>(t)));
+  }
+  b.total = off;
+  return SEGSALSA_OK;
+}
+
+// Launch shapes for the active images: prox launches grouped by workgroup
+// shape, one launch per FFT pass with the largest per-image shape.
+struct LaunchSet {
+  struct Group {
+    int kpw, nw, first, count, blocks;
+    size_t lds;
+  };
+  std::vector<Group> groups;
+  int nact = 0;
+  int row_blocks = 0, row_threads = 64, row_ept = 2, col_blocks = 0, col_threads = 64, col_ept = 2;
+  size_t row_lds = 0, col_lds = 0;
+};
+
+template <typename T>
+hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& active, void* const* zs,
+                         const void* const* ins, LaunchSet& ls, hipStream_t st) {
+  (void)ins;
+  const Common& c = b.c;
+  ls = LaunchSet();
+  ls.nact = (int)active.size();
+  // prox: sort by (nw, kpw) so each group is one launch over a contiguous range
+  std::vector<int> order(active);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const Plan& px = b.im[x].plan;
+    const Plan& py = b.im[y].plan;
+    return px.nw != py.nw ? px.nw < py.nw : px.kpw < py.kpw;
+  });
+  std::vector<ProxArgs<T>> pa(order.size()), pb;
+  for (size_t q = 0; q < order.size(); ++q) {
+    const ImgRun& r = b.im[order[q]];
+    const Plan& p = r.plan;
+    void* base = wsp<char>(ws, r.base);
+    if (ls.groups.empty() || ls.groups.back().nw != p.nw || ls.groups.back().kpw != p.kpw)
+      ls.groups.push_back({p.kpw, p.nw, (int)q, 0, 0, 0});
+    LaunchSet::Group& g = ls.groups.back();
+    ProxArgs<T>& a = pa[q];
+    std::memset(&a, 0, sizeof(a));
+    a.block0 = g.blocks;
+    a.g = p.g;
+    a.K = p.K;
+    a.nw = p.nw;
+    a.z = reinterpret_cast<T*>(zs[order[q]]);
+    a.phat = wsp<T>(base, p.off_phat);
+    a.dm = wsp<T>(base, p.off_dm);
+    a.d2 = wsp<T>(base, p.off_d2);
+    a.acc = wsp<T>(base, p.off_acc);
+    a.res_tile = nullptr;
+    a.mu = r.mu;
+    a.tau = r.lambda / r.mu;
+    a.pkind = c.pkind;
+    for (int j = 0; j < c.L; ++j) a.c[j] = (T)c.w[j];
+    g.count += 1;
+    g.blocks += p.g.ntiles();
+    g.lds = std::max(g.lds, p.prox_lds);
+  }
+  pb = pa;
+  for (size_t q = 0; q < order.size(); ++q) {
+    const ImgRun& r = b.im[order[q]];
+    pb[q].res_tile = wsp<double>(wsp<char>(ws, r.base), r.plan.off_restile);
+  }
+  // FFT passes: one launch each over all active images
+  std::vector<RowFwdArgs<T>> rf(active.size());
+  std::vector<ColArgs<T>> ca(active.size());
+  std::vector<RowInvArgs<T>> ri(active.size());
+  for (const int i : active) {
+    const Plan& p = b.im[i].plan;
+    ls.row_ept = std::max(ls.row_ept, p.row_ept);
+    ls.col_ept = std::max(ls.col_ept, p.col_ept);
+  }
+  int rb = 0, cb = 0;
+  for (size_t q = 0; q < active.size(); ++q) {
+    const ImgRun& r = b.im[active[q]];
+    const Plan& p = r.plan;
+    void* base = wsp<char>(ws, r.base);
+    double wsum = 0.0;
+    for (int j = 0; j < c.L; ++j) {
+      const double cj = (double)(T)c.w[j];  // the multiplier J applies, rounded to T
+      wsum += cj * cj;
+    }
+    RowFwdArgs<T>& f = rf[q];
+    std::memset(&f, 0, sizeof(f));
+    f.block0 = rb;
+    f.g = p.g;
+    f.K = p.K;
+    f.P = p.P;
+    f.rows_per_block = p.rows_per_block;
+    f.acc = wsp<T>(base, p.off_acc);
+    f.frow = wsp<int>(base, p.off_frow);
+    f.fcol = wsp<int>(base, p.off_fcol);
+    f.spec = wsp<C2<T>>(base, p.off_spec);
+    f.tw = wsp<C2<T>>(base, p.off_twW);
+    f.plan = p.frow;
+    ColArgs<T>& k = ca[q];
+    std::memset(&k, 0, sizeof(k));
+    k.block0 = cb;
+    k.H = p.H; k.W = p.W; k.P = p.P;
+    k.cols_per_block = p.cols_per_block;
+    k.spec = f.spec;
+    k.tw = wsp<C2<T>>(base, p.off_twH);
+    k.sx = wsp<double>(base, p.off_sx);
+    k.sy = wsp<double>(base, p.off_sy);
+    k.wsum = wsum;
+    k.scale = 1.0 / ((double)p.H * (double)p.W);
+    k.plan = p.fcol;
+    RowInvArgs<T>& v = ri[q];
+    std::memset(&v, 0, sizeof(v));
+    v.block0 = rb;
+    v.H = p.H; v.W = p.W; v.K = p.K; v.P = p.P;
+    v.rows_per_block = p.rows_per_block;
+    v.spec = f.spec;
+    v.z = reinterpret_cast<T*>(zs[active[q]]);
+    v.tw = f.tw;
+    v.plan = p.frow;
+    rb += p.P * ceil_div(p.H, p.rows_per_block);
+    cb += p.P * ceil_div(p.W, p.cols_per_block);
+    const long long ritems = (long long)p.rows_per_block * p.W, citems = (long long)p.cols_per_block * p.H;
+    ls.row_threads = std::max<int>(ls.row_threads, (int)((ritems + ls.row_ept - 1) / ls.row_ept));
+    ls.col_threads = std::max<int>(ls.col_threads, (int)((citems + ls.col_ept - 1) / ls.col_ept));
+    ls.row_lds = std::max(ls.row_lds, p.row_lds);
+    ls.col_lds = std::max(ls.col_lds, p.col_lds);
+  }
+  ls.row_threads = std::min(1024, (ls.row_threads + 63) / 64 * 64);
+  ls.col_threads = std::min(1024, (ls.col_threads + 63) / 64 * 64);
+  ls.row_blocks = rb;
+  ls.col_blocks = cb;
+  hipError_t e;
+  if (!pa.empty()) {
+    if ((e = launch_store(wsp<char>(ws, b.off_tab[0]), pa.data(), pa.size() * sizeof(pa[0]), st)) != hipSuccess) return e;
+    if ((e = launch_store(wsp<char>(ws, b.off_tab[1]), pb.data(), pb.size() * sizeof(pb[0]), st)) != hipSuccess) return e;
+    if ((e = launch_store(wsp<char>(ws, b.off_tab[2]), rf.data(), rf.size() * sizeof(rf[0]), st)) != hipSuccess) return e;
+    if ((e = launch_store(wsp<char>(ws, b.off_tab[3]), ca.data(), ca.size() * sizeof(ca[0]), st)) != hipSuccess) return e;
+    if ((e = launch_store(wsp<char>(ws, b.off_tab[4]), ri.data(), ri.size() * sizeof(ri[0]), st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, bool residuals) {
+  if (ls.nact == 0) return hipSuccess;
+  hipError_t e;
+  const ProxArgs<T>* ptab = wsp<ProxArgs<T>>(ws, b.off_tab[residuals ? 1 : 0]);
+  {
+    PhaseTimer t0(0, st);
+    for (const auto& g : ls.groups) {
+      e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.lds, st);
+      if (e != hipSuccess) return e;
+    }
+    t0.stop();
+  }
   PhaseTimer t1(1, st);
-  e = launch_rows_fwd(rf, p.row_ept, p.row_threads, p.row_lds, st);
+  e = launch_rows_fwd(wsp<RowFwdArgs<T>>(ws, b.off_tab[2]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
+                      ls.row_lds, st);
   t1.stop();
   if (e != hipSuccess) return e;
-
-  double wsum = 0.0;
-  for (int j = 0; j < p.L; ++j) {
-    const double cj = (double)(T)pr->patch_weights[j];  // the multiplier J applies, rounded to T
-    wsum += cj * cj;
-  }
-  ColArgs<T> ca;
-  ca.H = p.H; ca.W = p.W; ca.P = p.P;
-  ca.cols_per_block = p.cols_per_block;
-  ca.spec = rf.spec;
-  ca.tw = wsp<C2<T>>(ws, p.off_twH);
-  ca.sx = wsp<double>(ws, p.off_sx);
-  ca.sy = wsp<double>(ws, p.off_sy);
-  ca.wsum = wsum;
-  ca.scale = 1.0 / ((double)p.H * (double)p.W);
-  ca.plan = p.fcol;
   PhaseTimer t2(2, st);
-  e = launch_cols(ca, p.col_ept, p.col_threads, p.col_lds, st);
+  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads, ls.col_lds,
+                  st);
   t2.stop();
   if (e != hipSuccess) return e;
-
-  RowInvArgs<T> ri;
-  ri.H = p.H; ri.W = p.W; ri.K = p.K; ri.P = p.P;
-  ri.rows_per_block = p.rows_per_block;
-  ri.spec = rf.spec;
-  ri.z = z;
-  ri.tw = rf.tw;
-  ri.plan = p.frow;
   PhaseTimer t3(3, st);
-  e = launch_rows_inv(ri, p.row_ept, p.row_threads, p.row_lds, st);
+  e = launch_rows_inv(wsp<RowInvArgs<T>>(ws, b.off_tab[4]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
+                      ls.row_lds, st);
   t3.stop();
   return e;
 }
 
 template <typename T>
-segsalsa_status solve_t(const Plan& p, const segsalsa_problem* pr, const void* input, void* z_out, void* ws,
-                        segsalsa_stats* stats, hipStream_t st) {
-  T* z = reinterpret_cast<T*>(z_out);
-  hipError_t e;
-  SetupArgs<T> sa;
-  sa.g = p.g;
-  sa.frow = wsp<int>(ws, p.off_frow);
-  sa.fcol = wsp<int>(ws, p.off_fcol);
-  sa.H = p.H; sa.W = p.W;
-  sa.twW = wsp<C2<T>>(ws, p.off_twW);
-  sa.twH = wsp<C2<T>>(ws, p.off_twH);
-  sa.sx = wsp<double>(ws, p.off_sx);
-  sa.sy = wsp<double>(ws, p.off_sy);
-  if ((e = launch_setup(sa, st)) != hipSuccess) return hip_fail(e, "setup kernel");
-  if (!pr->warm_start) {
-    if ((e = launch_fill_zero(wsp<char>(ws, p.off_flags), 64, st)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_fill_zero(wsp<char>(ws, p.off_d2), p.off_acc - p.off_d2, st)) != hipSuccess)
-      return hip_fail(e, "fill");
-    InitArgs<T> ia;
-    ia.g = p.g;
-    ia.K = p.K;
-    ia.is_logits = pr->input_is_logits;
-    ia.input = reinterpret_cast<const T*>(input);
-    ia.z = z;
-    ia.phat = wsp<T>(ws, p.off_phat);
-    ia.dm = wsp<T>(ws, p.off_dm);
-    ia.flags = wsp<int>(ws, p.off_flags);
-    if ((e = launch_init(ia, st)) != hipSuccess) return hip_fail(e, "init kernel");
-  }
+DiagArgs<T> diag_args(const Batch& b, int i, void* ws, void* z) {
+  const ImgRun& r = b.im[i];
+  const Plan& p = r.plan;
+  void* base = wsp<char>(ws, r.base);
   DiagArgs<T> da;
   std::memset(&da, 0, sizeof(da));
   da.g = p.g;
   da.K = p.K;
-  da.pkind = pr->schatten_p == 1.0 ? kSchatten1 : (pr->schatten_p == 2.0 ? kSchatten2 : kSchattenInf);
-  da.lambda = pr->lambda;
+  da.pkind = b.c.pkind;
+  da.lambda = r.lambda;
   for (int j = 0; j < p.L; ++j) {
-    da.cw[j] = (double)(T)pr->patch_weights[j];
+    da.cw[j] = (double)(T)b.c.w[j];
     da.wsum += da.cw[j] * da.cw[j];
   }
-  da.z = z;
-  da.zprev = wsp<T>(ws, p.off_zprev);
-  da.phat = wsp<T>(ws, p.off_phat);
-  da.partial = wsp<double>(ws, p.off_partial);
-  da.out = wsp<double>(ws, p.off_out);
-  const size_t nel = (size_t)p.K * p.H * p.W;
-  const int every = pr->residual_every;
-  double rp = 0.0, rd = 0.0;
-  int done = 0;
-  for (int it = 0; it < pr->iters; ++it) {
-    const bool checked = every > 0 && ((it + 1) % every == 0 || it + 1 == pr->iters);
-    if (checked && (e = launch_copy(z, da.zprev, nel, st)) != hipSuccess) return hip_fail(e, "copy z");
-    if ((e = enqueue_round<T>(p, pr, z, ws, st, checked)) != hipSuccess) return hip_fail(e, "round");
-    done = it + 1;
-    if (!checked) continue;
-    if ((e = launch_reduce(wsp<double>(ws, p.off_restile), p.g.ntiles(), da.out, 0, st)) != hipSuccess)
-      return hip_fail(e, "residual reduce");
-    if ((e = launch_dual_res(da, st)) != hipSuccess) return hip_fail(e, "dual residual");
-    double host[2];
-    if ((e = hipMemcpyAsync(host, da.out, sizeof(host), hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return hip_fail(e, "residual copy");
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "stream sync");
-    rp = std::sqrt(std::max(host[0], 0.0));
-    rd = pr->mu * std::sqrt(std::max(host[1], 0.0));
-    if (pr->tol > 0.0 && rp <= pr->tol && rd <= pr->tol) break;  // stopping rule of Sec. 4
-  }
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    int flags = 0;
-    double obj = 0.0;
-    if (every > 0) {
-      if ((e = launch_objective(da, st)) != hipSuccess) return hip_fail(e, "objective");
-      if ((e = hipMemcpyAsync(&obj, da.out + 2, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
-        return hip_fail(e, "objective copy");
+  da.z = reinterpret_cast<T*>(z);
+  da.zprev = wsp<T>(base, p.off_zprev);
+  da.phat = wsp<T>(base, p.off_phat);
+  da.partial = wsp<double>(base, p.off_partial);
+  da.out = wsp<double>(base, p.off_out);
+  return da;
+}
+
+// Set-up and initialisation of every image, then all rounds.
+template <typename T>
+hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
+                         LaunchSet& ls) {
+  hipError_t e;
+  const Common& c = b.c;
+  const int n = (int)b.im.size();
+  for (int i = 0; i < n; ++i) {
+    const ImgRun& r = b.im[i];
+    const Plan& p = r.plan;
+    void* base = wsp<char>(ws, r.base);
+    SetupArgs<T> sa;
+    sa.g = p.g;
+    sa.frow = wsp<int>(base, p.off_frow);
+    sa.fcol = wsp<int>(base, p.off_fcol);
+    sa.H = p.H;
+    sa.W = p.W;
+    sa.twW = wsp<C2<T>>(base, p.off_twW);
+    sa.twH = wsp<C2<T>>(base, p.off_twH);
+    sa.sx = wsp<double>(base, p.off_sx);
+    sa.sy = wsp<double>(base, p.off_sy);
+    if ((e = launch_setup(sa, st)) != hipSuccess) return e;
+    if (!c.warm) {
+      if ((e = launch_fill_zero(wsp<char>(base, p.off_flags), 64, st)) != hipSuccess) return e;
+      if ((e = launch_fill_zero(wsp<char>(base, p.off_d2), p.off_acc - p.off_d2, st)) != hipSuccess) return e;
+      InitArgs<T> ia;
+      ia.g = p.g;
+      ia.K = p.K;
+      ia.is_logits = c.logits;
+      ia.input = reinterpret_cast<const T*>(ins[i]);
+      ia.z = reinterpret_cast<T*>(zs[i]);
+      ia.phat = wsp<T>(base, p.off_phat);
+      ia.dm = wsp<T>(base, p.off_dm);
+      ia.flags = wsp<int>(base, p.off_flags);
+      if ((e = launch_init(ia, st)) != hipSuccess) return e;
     }
-    if ((e = hipMemcpyAsync(&flags, wsp<int>(ws, p.off_flags), sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return hip_fail(e, "flags copy");
+  }
+  std::vector<int> active(n);
+  for (int i = 0; i < n; ++i) active[i] = i;
+  if ((e = upload_tables<T>(b, ws, active, zs, ins, ls, st)) != hipSuccess) return e;
+  if (c.every == 0) {
+    for (int it = 0; it < c.iters; ++it)
+      if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Rounds with residual checks: every `every` rounds (and after the last) the
+// residuals of each active image are read back; with tol > 0, images whose
+// primal and dual residuals are both <= tol stop (the stopping rule of Sec. 4)
+// and the launch tables are rebuilt without them.
+template <typename T>
+segsalsa_status run_checked(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
+                            LaunchSet& ls, segsalsa_stats* stats) {
+  const Common& c = b.c;
+  const int n = (int)b.im.size();
+  hipError_t e;
+  std::vector<int> active(n), done(n, 0);
+  std::vector<double> rp(n, 0.0), rd(n, 0.0);
+  for (int i = 0; i < n; ++i) active[i] = i;
+  std::vector<double> host(2 * (size_t)n);
+  for (int it = 0; it < c.iters && !active.empty(); ++it) {
+    const bool checked = (it + 1) % c.every == 0 || it + 1 == c.iters;
+    if (checked)
+      for (const int i : active) {
+        const Plan& p = b.im[i].plan;
+        DiagArgs<T> da = diag_args<T>(b, i, ws, zs[i]);
+        if ((e = launch_copy(da.z, da.zprev, (size_t)p.K * p.H * p.W, st)) != hipSuccess) return hip_fail(e, "copy z");
+      }
+    if ((e = enqueue_round<T>(b, ls, ws, st, checked)) != hipSuccess) return hip_fail(e, "round");
+    for (const int i : active) done[i] = it + 1;
+    if (!checked) continue;
+    for (size_t q = 0; q < active.size(); ++q) {
+      const int i = active[q];
+      const Plan& p = b.im[i].plan;
+      DiagArgs<T> da = diag_args<T>(b, i, ws, zs[i]);
+      void* base = wsp<char>(ws, b.im[i].base);
+      if ((e = launch_reduce(wsp<double>(base, p.off_restile), p.g.ntiles(), da.out, 0, st)) != hipSuccess)
+        return hip_fail(e, "residual reduce");
+      if ((e = launch_dual_res(da, st)) != hipSuccess) return hip_fail(e, "dual residual");
+      if ((e = hipMemcpyAsync(&host[2 * q], da.out, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e, "residual copy");
+    }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "stream sync");
-    stats->flags = flags;
-    stats->rounds_done = done;
-    stats->primal_res = rp;
-    stats->dual_res = rd;
-    stats->objective = obj;
+    std::vector<int> still;
+    for (size_t q = 0; q < active.size(); ++q) {
+      const int i = active[q];
+      rp[i] = std::sqrt(std::max(host[2 * q], 0.0));
+      rd[i] = b.im[i].mu * std::sqrt(std::max(host[2 * q + 1], 0.0));
+      if (!(c.tol > 0.0 && rp[i] <= c.tol && rd[i] <= c.tol)) still.push_back(i);
+    }
+    if (still.size() != active.size()) {
+      active.swap(still);
+      if ((e = upload_tables<T>(b, ws, active, zs, ins, ls, st)) != hipSuccess) return hip_fail(e, "tables");
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    stats[i].primal_res = rp[i];
+    stats[i].dual_res = rd[i];
+    stats[i].rounds_done = done[i];
   }
   return SEGSALSA_OK;
 }
 
-segsalsa_status state_common(const segsalsa_problem* prob, segsalsa_precision precision, const void* ws,
-                                    size_t bytes, Plan& p) {
-  segsalsa_status s = make_plan(prob, precision, p);
+// Fill stats after the rounds: input flags, and the objective when residuals were asked for.
+template <typename T>
+segsalsa_status finish_stats(const Batch& b, void* ws, void* const* zs, hipStream_t st, segsalsa_stats* stats) {
+  const int n = (int)b.im.size();
+  hipError_t e;
+  std::vector<int> flags(n, 0);
+  std::vector<double> obj(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const ImgRun& r = b.im[i];
+    void* base = wsp<char>(ws, r.base);
+    if (b.c.every > 0) {
+      DiagArgs<T> da = diag_args<T>(b, i, ws, zs[i]);
+      if ((e = launch_objective(da, st)) != hipSuccess) return hip_fail(e, "objective");
+      if ((e = hipMemcpyAsync(&obj[i], da.out + 2, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e, "objective copy");
+    }
+    if ((e = hipMemcpyAsync(&flags[i], wsp<int>(base, r.plan.off_flags), sizeof(int), hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+      return hip_fail(e, "flags copy");
+  }
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "stream sync");
+  for (int i = 0; i < n; ++i) {
+    stats[i].flags = flags[i];
+    stats[i].objective = obj[i];
+  }
+  return SEGSALSA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Whole-solve hipGraphs: captured once per (workspace, buffers, problem) and
+// replayed, so a solve is one graph launch.
+// ---------------------------------------------------------------------------
+struct GraphEntry {
+  std::vector<unsigned char> key;
+  int device;
+  hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;   // most recent last
+constexpr size_t kGraphCache = 8;
+
+void key_add(std::vector<unsigned char>& k, const void* p, size_t n) {
+  const unsigned char* c = reinterpret_cast<const unsigned char*>(p);
+  k.insert(k.end(), c, c + n);
+}
+
+std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, const void* const* ins) {
+  std::vector<unsigned char> k;
+  key_add(k, &b.c, sizeof(b.c));
+  key_add(k, &ws, sizeof(ws));
+  for (size_t i = 0; i < b.im.size(); ++i) {
+    const ImgRun& r = b.im[i];
+    key_add(k, &r.plan.K, sizeof(int));
+    key_add(k, &r.plan.H, sizeof(int));
+    key_add(k, &r.plan.W, sizeof(int));
+    key_add(k, &r.lambda, sizeof(double));
+    key_add(k, &r.mu, sizeof(double));
+    key_add(k, &zs[i], sizeof(void*));
+    key_add(k, &ins[i], sizeof(void*));
+  }
+  // plan choices that environment overrides can change
+  for (size_t i = 0; i < b.im.size(); ++i) {
+    key_add(k, &b.im[i].plan.g, sizeof(TileGeom));
+    key_add(k, &b.im[i].plan.kpw, sizeof(int));
+  }
+  return k;
+}
+
+hipStream_t capture_stream(int device) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)streams.size() <= device) streams.resize(device + 1, nullptr);
+  if (!streams[device]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[device] = s;
+  }
+  return streams[device];
+}
+
+template <typename T>
+segsalsa_status run_graph(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::vector<unsigned char> key = graph_key(b, ws, zs, ins);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size(); ++i) {
+    if (g_graphs[i].device == dev && g_graphs[i].key == key) {
+      GraphEntry ent = g_graphs[i];
+      g_graphs.erase(g_graphs.begin() + i);
+      g_graphs.push_back(ent);
+      e = hipGraphLaunch(ent.exec, st);
+      return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "hipGraphLaunch");
+    }
+  }
+  hipStream_t cs = capture_stream(dev);
+  if (!cs) return fail(SEGSALSA_ERR_DEVICE, "cannot create the capture stream");
+  LaunchSet ls;
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) return hip_fail(e, "begin capture");
+  hipError_t ee = enqueue_solve<T>(b, ws, zs, ins, cs, ls);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  if (ee != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return hip_fail(ee, "capture");
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  if (g_graphs.size() >= kGraphCache) {
+    hipGraphExecDestroy(g_graphs.front().exec);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back({key, dev, exec});
+  e = hipGraphLaunch(exec, st);
+  return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+template <typename T>
+segsalsa_status solve_batch_t(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
+                              segsalsa_stats* stats) {
+  const int n = (int)b.im.size();
+  if (b.c.graph) {
+    segsalsa_status s = run_graph<T>(b, ws, zs, ins, st);
+    if (s != SEGSALSA_OK) return s;
+  } else {
+    LaunchSet ls;
+    hipError_t e = enqueue_solve<T>(b, ws, zs, ins, st, ls);
+    if (e != hipSuccess) return hip_fail(e, "enqueue");
+    if (b.c.every > 0) {
+      segsalsa_status s = run_checked<T>(b, ws, zs, ins, st, ls, stats);
+      if (s != SEGSALSA_OK) return s;
+    }
+  }
+  if (stats) {
+    if (b.c.every == 0)
+      for (int i = 0; i < n; ++i) {
+        std::memset(&stats[i], 0, sizeof(stats[i]));
+        stats[i].rounds_done = b.c.iters;
+      }
+    return finish_stats<T>(b, ws, zs, st, stats);
+  }
+  return SEGSALSA_OK;
+}
+
+segsalsa_status single_batch(const segsalsa_problem* pr, segsalsa_precision prec, Batch& b) {
+  Common c;
+  segsalsa_status s = validate_problem(pr, prec, c);
   if (s != SEGSALSA_OK) return s;
-  return check_ws(p, ws, bytes);
+  return make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, b);
 }
 
 template <typename T>
 hipError_t run_state(const Plan& p, void* ws, int to_canon, const void* ph, const void* d1, const void* d2,
-                            const void* d3, const void* d4, hipStream_t st) {
+                     const void* d3, const void* d4, hipStream_t st) {
   StateArgs<T> a;
   a.g = p.g;
   a.K = p.K;
@@ -550,10 +922,10 @@ segsalsa_status segsalsa_str_workspace_size(const segsalsa_problem* prob, segsal
                                             size_t* bytes) {
   g_last_error.clear();
   if (!bytes) return fail(SEGSALSA_ERR_INVALID_ARG, "bytes is NULL");
-  Plan p;
-  segsalsa_status s = make_plan(prob, precision, p);
+  Batch b;
+  segsalsa_status s = single_batch(prob, precision, b);
   if (s != SEGSALSA_OK) return s;
-  *bytes = p.total;
+  *bytes = b.total;
   return SEGSALSA_OK;
 }
 
@@ -561,19 +933,100 @@ segsalsa_status segsalsa_str_solve(const segsalsa_problem* prob, segsalsa_precis
                                    void* z_out, void* workspace, size_t workspace_bytes, segsalsa_stats* stats,
                                    hipStream_t stream) {
   g_last_error.clear();
-  Plan p;
-  segsalsa_status s = make_plan(prob, precision, p);
+  Batch b;
+  segsalsa_status s = single_batch(prob, precision, b);
   if (s != SEGSALSA_OK) return s;
+  const size_t ts = b.c.ts;
   if (!z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "z_out is NULL");
   if (!prob->warm_start && !input) return fail(SEGSALSA_ERR_INVALID_ARG, "input is NULL");
   if (input && input == z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "z_out aliases input");
-  if (reinterpret_cast<uintptr_t>(z_out) % p.ts || reinterpret_cast<uintptr_t>(input) % p.ts)
+  if (reinterpret_cast<uintptr_t>(z_out) % ts || reinterpret_cast<uintptr_t>(input) % ts)
     return fail(SEGSALSA_ERR_INVALID_ARG, "input/z_out not aligned to the element size");
   if ((prob->residual_every > 0 || prob->tol > 0.0) && !stats)
     return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every / tol need a stats pointer");
-  if ((s = check_ws(p, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
-  return p.fp64 ? solve_t<double>(p, prob, input, z_out, workspace, stats, stream)
-                : solve_t<float>(p, prob, input, z_out, workspace, stats, stream);
+  if ((s = check_ws(b.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
+  void* zs[1] = {z_out};
+  const void* ins[1] = {input};
+  return b.c.fp64 ? solve_batch_t<double>(b, workspace, zs, ins, stream, stats)
+                  : solve_batch_t<float>(b, workspace, zs, ins, stream, stats);
+}
+
+static segsalsa_status batch_common(int32_t n, const segsalsa_image* imgs, const segsalsa_batch_params* bp,
+                                    segsalsa_precision precision, Batch& b) {
+  if (n < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "n_images = %d < 1", n);
+  if (!imgs || !bp) return fail(SEGSALSA_ERR_INVALID_ARG, "images / params is NULL");
+  Common c;
+  segsalsa_status s = validate_common(bp->patch_radius, bp->patch_weights, bp->schatten_p, bp->iters,
+                                      bp->input_is_logits, bp->residual_every, bp->tol, bp->warm_start, bp->use_graph,
+                                      precision, c);
+  if (s != SEGSALSA_OK) return s;
+  std::vector<int> K(n), H(n), W(n);
+  std::vector<double> lam(n), mu(n);
+  for (int i = 0; i < n; ++i) {
+    K[i] = imgs[i].K;
+    H[i] = imgs[i].H;
+    W[i] = imgs[i].W;
+    lam[i] = imgs[i].lambda;
+    mu[i] = imgs[i].mu;
+  }
+  s = make_batch(n, K.data(), H.data(), W.data(), lam.data(), mu.data(), c, b);
+  if (s != SEGSALSA_OK) return s;
+  for (int i = 0; i < n; ++i) {
+    b.im[i].in_off = (size_t)imgs[i].in_offset;
+    b.im[i].out_off = (size_t)imgs[i].out_offset;
+    if (imgs[i].in_offset < 0 || imgs[i].out_offset < 0)
+      return fail(SEGSALSA_ERR_INVALID_ARG, "image %d: negative offset", i);
+  }
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_batch_workspace_size(int32_t n_images, const segsalsa_image* images,
+                                                  const segsalsa_batch_params* params, segsalsa_precision precision,
+                                                  size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(SEGSALSA_ERR_INVALID_ARG, "bytes is NULL");
+  Batch b;
+  segsalsa_status s = batch_common(n_images, images, params, precision, b);
+  if (s != SEGSALSA_OK) return s;
+  *bytes = b.total;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_solve_batch(int32_t n_images, const segsalsa_image* images,
+                                         const segsalsa_batch_params* params, segsalsa_precision precision,
+                                         const void* input_packed, void* z_packed, void* workspace,
+                                         size_t workspace_bytes, segsalsa_stats* stats, hipStream_t stream) {
+  g_last_error.clear();
+  Batch b;
+  segsalsa_status s = batch_common(n_images, images, params, precision, b);
+  if (s != SEGSALSA_OK) return s;
+  if (!z_packed) return fail(SEGSALSA_ERR_INVALID_ARG, "z_packed is NULL");
+  if (!params->warm_start && !input_packed) return fail(SEGSALSA_ERR_INVALID_ARG, "input_packed is NULL");
+  const size_t ts = b.c.ts;
+  if (reinterpret_cast<uintptr_t>(z_packed) % ts || reinterpret_cast<uintptr_t>(input_packed) % ts)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "input/z not aligned to the element size");
+  if ((params->residual_every > 0 || params->tol > 0.0) && !stats)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every / tol need a stats array");
+  // output ranges must not overlap each other or any input range
+  std::vector<std::pair<size_t, size_t>> outs;
+  for (int i = 0; i < n_images; ++i) {
+    const size_t nel = (size_t)images[i].K * images[i].H * images[i].W;
+    outs.push_back({b.im[i].out_off, b.im[i].out_off + nel});
+  }
+  std::vector<std::pair<size_t, size_t>> sorted = outs;
+  std::sort(sorted.begin(), sorted.end());
+  for (size_t i = 1; i < sorted.size(); ++i)
+    if (sorted[i].first < sorted[i - 1].second) return fail(SEGSALSA_ERR_INVALID_ARG, "output ranges overlap");
+  if (input_packed == z_packed) return fail(SEGSALSA_ERR_INVALID_ARG, "z_packed aliases input_packed");
+  if ((s = check_ws(b.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
+  std::vector<void*> zs(n_images);
+  std::vector<const void*> ins(n_images);
+  for (int i = 0; i < n_images; ++i) {
+    zs[i] = reinterpret_cast<char*>(z_packed) + b.im[i].out_off * ts;
+    ins[i] = input_packed ? reinterpret_cast<const char*>(input_packed) + b.im[i].in_off * ts : nullptr;
+  }
+  return b.c.fp64 ? solve_batch_t<double>(b, workspace, zs.data(), ins.data(), stream, stats)
+                  : solve_batch_t<float>(b, workspace, zs.data(), ins.data(), stream, stats);
 }
 
 segsalsa_status segsalsa_str_labels(int32_t K, int32_t H, int32_t W, segsalsa_precision precision, const void* z,
@@ -592,10 +1045,12 @@ segsalsa_status segsalsa_str_state_export(const segsalsa_problem* prob, segsalsa
                                           const void* workspace, size_t workspace_bytes, void* d1, void* d2, void* d3,
                                           void* d4, hipStream_t stream) {
   g_last_error.clear();
-  Plan p;
-  segsalsa_status s = state_common(prob, precision, workspace, workspace_bytes, p);
+  Batch b;
+  segsalsa_status s = single_batch(prob, precision, b);
   if (s != SEGSALSA_OK) return s;
+  if ((s = check_ws(b.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
   void* ws = const_cast<void*>(workspace);
+  const Plan& p = b.im[0].plan;
   hipError_t e = p.fp64 ? run_state<double>(p, ws, 1, nullptr, d1, d2, d3, d4, stream)
                         : run_state<float>(p, ws, 1, nullptr, d1, d2, d3, d4, stream);
   return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "state export kernel");
@@ -605,10 +1060,12 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem* prob, segsalsa
                                           size_t workspace_bytes, const void* p_hat, const void* d1, const void* d2,
                                           const void* d3, const void* d4, hipStream_t stream) {
   g_last_error.clear();
-  Plan p;
-  segsalsa_status s = state_common(prob, precision, workspace, workspace_bytes, p);
+  Batch b;
+  segsalsa_status s = single_batch(prob, precision, b);
   if (s != SEGSALSA_OK) return s;
+  if ((s = check_ws(b.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
   if (!p_hat || !d1 || !d2 || !d3 || !d4) return fail(SEGSALSA_ERR_INVALID_ARG, "state import needs all arrays");
+  const Plan& p = b.im[0].plan;
   hipError_t e = p.fp64 ? run_state<double>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream)
                         : run_state<float>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream);
   return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "state import kernel");
@@ -645,5 +1102,6 @@ segsalsa_status segsalsa_profile_read(double* ms, int64_t* launches, int32_t res
   }
   return SEGSALSA_OK;
 }
+
 
 }  // extern "C"

@@ -226,13 +226,15 @@ __device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs,
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T> a) {
+__global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc)];
+  const int bid = blockIdx.x - a.block0;
   const int H = a.g.H, W = a.g.W;
   const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
-  const int m = blockIdx.x / nrb;
-  const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
+  const int m = bid / nrb;
+  const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
   C2<T>* tw = buf + a.rows_per_block * W;
@@ -266,14 +268,16 @@ __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T> 
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T> a) {
+__global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const ColArgs<T>& a = descs[find_desc(descs, ndesc)];
+  const int bid = blockIdx.x - a.block0;
   const int H = a.H, W = a.W;
   const int CB = a.cols_per_block;
   const int ncb = (W + CB - 1) / CB;
-  const int m = blockIdx.x / ncb;
-  const int col0 = (blockIdx.x - m * ncb) * CB;
+  const int m = bid / ncb;
+  const int col0 = (bid - m * ncb) * CB;
   const int nb = min(CB, W - col0);
   C2<T>* sp = a.spec + (size_t)m * H * W + col0;
   C2<T>* tw = buf + CB * H;
@@ -298,13 +302,15 @@ __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T> a) {
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> a) {
+__global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const RowInvArgs<T>& a = descs[find_desc(descs, ndesc)];
+  const int bid = blockIdx.x - a.block0;
   const int H = a.H, W = a.W;
   const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
-  const int m = blockIdx.x / nrb;
-  const int row0 = (blockIdx.x - m * nrb) * a.rows_per_block;
+  const int m = bid / nrb;
+  const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const C2<T>* in = a.spec + ((size_t)m * H + row0) * W;
   C2<T>* tw = buf + a.rows_per_block * W;
@@ -324,7 +330,7 @@ __global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T> 
 }
 
 template <typename K, typename A>
-static hipError_t launch_fft(K fn, const A& a, int blocks, int threads, size_t lds, hipStream_t st) {
+static hipError_t launch_fft(K fn, const A* descs, int ndesc, int blocks, int threads, size_t lds, hipStream_t st) {
   static bool lds_set = false;  // one static per kernel instantiation; idempotent
   if (!lds_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -332,58 +338,35 @@ static hipError_t launch_fft(K fn, const A& a, int blocks, int threads, size_t l
     if (e != hipSuccess) return e;
     lds_set = true;
   }
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, descs, ndesc);
   return hipGetLastError();
 }
 
-template <typename T, typename A, typename F2, typename F4, typename F8, typename F16>
-static hipError_t launch_ept(int ept, F2 f2, F4 f4, F8 f8, F16 f16, const A& a, int blocks, int threads, size_t lds,
-                             hipStream_t st) {
+template <typename A, typename F2, typename F4, typename F8, typename F16>
+static hipError_t launch_ept(int ept, F2 f2, F4 f4, F8 f8, F16 f16, const A* d, int n, int blocks, int threads,
+                             size_t lds, hipStream_t st) {
   switch (ept) {
-    case 2: return launch_fft(f2, a, blocks, threads, lds, st);
-    case 4: return launch_fft(f4, a, blocks, threads, lds, st);
-    case 8: return launch_fft(f8, a, blocks, threads, lds, st);
-    case 16: return launch_fft(f16, a, blocks, threads, lds, st);
+    case 2: return launch_fft(f2, d, n, blocks, threads, lds, st);
+    case 4: return launch_fft(f4, d, n, blocks, threads, lds, st);
+    case 8: return launch_fft(f8, d, n, blocks, threads, lds, st);
+    case 16: return launch_fft(f16, d, n, blocks, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T>
-static hipError_t rows_fwd_t(const RowFwdArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  const int blocks = a.P * ((a.g.H + a.rows_per_block - 1) / a.rows_per_block);
-  return launch_ept<T>(ept, fft_rows_fwd_kernel<T, 2>, fft_rows_fwd_kernel<T, 4>, fft_rows_fwd_kernel<T, 8>, fft_rows_fwd_kernel<T, 16>, a,
-                       blocks, threads, lds, st);
-}
-template <typename T>
-static hipError_t cols_t(const ColArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  const int blocks = a.P * ((a.W + a.cols_per_block - 1) / a.cols_per_block);
-  return launch_ept<T>(ept, fft_cols_kernel<T, 2>, fft_cols_kernel<T, 4>, fft_cols_kernel<T, 8>, fft_cols_kernel<T, 16>, a, blocks,
-                       threads, lds, st);
-}
-template <typename T>
-static hipError_t rows_inv_t(const RowInvArgs<T>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  const int blocks = a.P * ((a.H + a.rows_per_block - 1) / a.rows_per_block);
-  return launch_ept<T>(ept, fft_rows_inv_kernel<T, 2>, fft_rows_inv_kernel<T, 4>, fft_rows_inv_kernel<T, 8>, fft_rows_inv_kernel<T, 16>, a,
-                       blocks, threads, lds, st);
-}
+#define SEG_FFT_LAUNCHER(NAME, ARGS, KERNEL)                                                                     \
+  hipError_t NAME(const ARGS<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st) {     \
+    return launch_ept(ept, KERNEL<float, 2>, KERNEL<float, 4>, KERNEL<float, 8>, KERNEL<float, 16>, d, n, blocks, \
+                      threads, lds, st);                                                                          \
+  }                                                                                                               \
+  hipError_t NAME(const ARGS<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st) {    \
+    return launch_ept(ept, KERNEL<double, 2>, KERNEL<double, 4>, KERNEL<double, 8>, KERNEL<double, 16>, d, n,     \
+                      blocks, threads, lds, st);                                                                  \
+  }
 
-hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return rows_fwd_t(a, ept, threads, lds, st);
-}
-hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return rows_fwd_t(a, ept, threads, lds, st);
-}
-hipError_t launch_cols(const ColArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return cols_t(a, ept, threads, lds, st);
-}
-hipError_t launch_cols(const ColArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return cols_t(a, ept, threads, lds, st);
-}
-hipError_t launch_rows_inv(const RowInvArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return rows_inv_t(a, ept, threads, lds, st);
-}
-hipError_t launch_rows_inv(const RowInvArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st) {
-  return rows_inv_t(a, ept, threads, lds, st);
-}
+SEG_FFT_LAUNCHER(launch_rows_fwd, RowFwdArgs, fft_rows_fwd_kernel)
+SEG_FFT_LAUNCHER(launch_cols, ColArgs, fft_cols_kernel)
+SEG_FFT_LAUNCHER(launch_rows_inv, RowInvArgs, fft_rows_inv_kernel)
+#undef SEG_FFT_LAUNCHER
 
 }  // namespace segsalsa

@@ -122,6 +122,28 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+struct StoreBlob {
+  unsigned char b[2048];
+};
+
+__global__ void store_kernel(unsigned char* dst, StoreBlob blob, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = blob.b[i];
+}
+
+hipError_t launch_store(void* dst, const void* src, size_t n, hipStream_t st) {
+  const unsigned char* s = reinterpret_cast<const unsigned char*>(src);
+  unsigned char* d = reinterpret_cast<unsigned char*>(dst);
+  for (size_t off = 0; off < n; off += sizeof(StoreBlob)) {
+    StoreBlob blob;
+    const size_t len = n - off < sizeof(StoreBlob) ? n - off : sizeof(StoreBlob);
+    for (size_t i = 0; i < len; ++i) blob.b[i] = s[off + i];
+    hipLaunchKernelGGL(store_kernel, dim3(1), dim3(256), 0, st, d + off, blob, (int)len);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Tile layout <-> canonical layouts, one thread per (pixel, class).
 template <typename T>
 __global__ void state_kernel(const StateArgs<T> a) {

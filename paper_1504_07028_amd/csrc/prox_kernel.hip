@@ -91,11 +91,12 @@ __device__ inline double data_prox_gain(double s, double q, double mu) {
 
 template <typename T, int M, int KPW>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
-prox_rhs_kernel(const ProxArgs<T> a) {
+prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
   constexpr int L = D * D;
+  const ProxArgs<T>& a = descs[find_desc(descs, ndesc)];
   const TileGeom& g = a.g;
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x - a.block0;
   const int tr = tile / g.ntc;
   const int tc = tile - tr * g.ntc;
   const int r0 = g.r0(tr), c0 = g.c0(tc);
@@ -304,7 +305,8 @@ prox_rhs_kernel(const ProxArgs<T> a) {
 }
 
 template <typename T, int M, int KPW>
-static hipError_t launch_prox_t(const ProxArgs<T>& a, size_t lds, hipStream_t st) {
+static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks, int threads, size_t lds,
+                                hipStream_t st) {
   auto fn = prox_rhs_kernel<T, M, KPW>;
   static bool lds_set = false;  // idempotent, so a racing second call is harmless
   if (!lds_set) {
@@ -313,38 +315,42 @@ static hipError_t launch_prox_t(const ProxArgs<T>& a, size_t lds, hipStream_t st
     if (e != hipSuccess) return e;
     lds_set = true;
   }
-  hipLaunchKernelGGL(fn, dim3(a.g.ntiles()), dim3(a.nw * 64), lds, st, a);
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, descs, ndesc);
   return hipGetLastError();
 }
 
 template <typename T, int M>
-static hipError_t launch_prox_m(const ProxArgs<T>& a, int kpw, size_t lds, hipStream_t st) {
+static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, size_t lds,
+                                hipStream_t st) {
   switch (kpw) {
-    case 1: return launch_prox_t<T, M, 1>(a, lds, st);
-    case 2: return launch_prox_t<T, M, 2>(a, lds, st);
-    case 4: return launch_prox_t<T, M, 4>(a, lds, st);
+    case 1: return launch_prox_t<T, M, 1>(d, n, blocks, threads, lds, st);
+    case 2: return launch_prox_t<T, M, 2>(d, n, blocks, threads, lds, st);
+    case 4: return launch_prox_t<T, M, 4>(d, n, blocks, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
-static hipError_t launch_prox_any(const ProxArgs<T>& a, int kpw, size_t lds, hipStream_t st) {
-  switch (a.g.M) {
-    case 0: return launch_prox_m<T, 0>(a, kpw, lds, st);
-    case 1: return launch_prox_m<T, 1>(a, kpw, lds, st);
-    case 2: return launch_prox_m<T, 2>(a, kpw, lds, st);
-    case 3: return launch_prox_m<T, 3>(a, kpw, lds, st);
-    case 4: return launch_prox_m<T, 4>(a, kpw, lds, st);
-    case 5: return launch_prox_m<T, 5>(a, kpw, lds, st);
+static hipError_t launch_prox_any(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                                  hipStream_t st) {
+  switch (M) {
+    case 0: return launch_prox_m<T, 0>(d, n, blocks, threads, kpw, lds, st);
+    case 1: return launch_prox_m<T, 1>(d, n, blocks, threads, kpw, lds, st);
+    case 2: return launch_prox_m<T, 2>(d, n, blocks, threads, kpw, lds, st);
+    case 3: return launch_prox_m<T, 3>(d, n, blocks, threads, kpw, lds, st);
+    case 4: return launch_prox_m<T, 4>(d, n, blocks, threads, kpw, lds, st);
+    case 5: return launch_prox_m<T, 5>(d, n, blocks, threads, kpw, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_prox(const ProxArgs<float>& a, int kpw, size_t lds, hipStream_t st) {
-  return launch_prox_any<float>(a, kpw, lds, st);
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                       hipStream_t st) {
+  return launch_prox_any<float>(d, n, blocks, threads, M, kpw, lds, st);
 }
-hipError_t launch_prox(const ProxArgs<double>& a, int kpw, size_t lds, hipStream_t st) {
-  return launch_prox_any<double>(a, kpw, lds, st);
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                       hipStream_t st) {
+  return launch_prox_any<double>(d, n, blocks, threads, M, kpw, lds, st);
 }
 
 }  // namespace segsalsa

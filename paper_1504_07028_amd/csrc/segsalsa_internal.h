@@ -94,8 +94,23 @@ __host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, 
 // Per-pixel arithmetic parameters of one round.
 enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3 };
 
+// Per-image kernel arguments live in device tables; a launch covers a range
+// of images and block b belongs to the last image whose block0 <= b.
+template <typename D>
+__device__ inline int find_desc(const D* descs, int n) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <typename T>
 struct ProxArgs {
+  int block0;                 // first block of this image in the launch
   TileGeom g;
   int K;
   int nw;                     // wavefronts per workgroup
@@ -118,6 +133,7 @@ struct FftPlanDev {
 
 template <typename T>
 struct RowFwdArgs {
+  int block0;
   TileGeom g;
   int K, P;
   int rows_per_block;
@@ -131,6 +147,7 @@ struct RowFwdArgs {
 
 template <typename T>
 struct ColArgs {
+  int block0;
   int H, W, P;
   int cols_per_block;
   C2<T>* __restrict__ spec;
@@ -144,6 +161,7 @@ struct ColArgs {
 
 template <typename T>
 struct RowInvArgs {
+  int block0;
   int H, W, K, P;
   int rows_per_block;
   const C2<T>* __restrict__ spec;

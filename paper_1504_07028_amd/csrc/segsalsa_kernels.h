@@ -36,15 +36,18 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
 #undef SEG_CASE
 }
 
-hipError_t launch_prox(const ProxArgs<float>& a, int kpw, size_t lds, hipStream_t st);
-hipError_t launch_prox(const ProxArgs<double>& a, int kpw, size_t lds, hipStream_t st);
+// Per-round launches over a table of per-image descriptors in device memory.
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                       hipStream_t st);
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                       hipStream_t st);
 
-hipError_t launch_rows_fwd(const RowFwdArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_fwd(const RowFwdArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<float>& a, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<double>& a, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols(const ColArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
 
 // Set-up, initialisation and data-movement kernels (misc_kernels.hip).
 template <typename T>
@@ -76,6 +79,9 @@ hipError_t launch_init(const InitArgs<float>& a, hipStream_t st);
 hipError_t launch_init(const InitArgs<double>& a, hipStream_t st);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+// Copy n host bytes into device memory through kernel arguments (no host
+// staging buffer has to outlive the call; capturable in a graph).
+hipError_t launch_store(void* dst, const void* src, size_t n, hipStream_t st);
 
 // Conversion between the tile layout and canonical class-planar arrays.
 template <typename T>

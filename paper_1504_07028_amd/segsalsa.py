@@ -38,8 +38,19 @@ class segsalsa_problem(ctypes.Structure):
         ("patch_weights", POINTER(c_double)),
         ("schatten_p", c_double), ("lambda_", c_double), ("mu", c_double),
         ("iters", c_int32), ("input_is_logits", c_int32), ("residual_every", c_int32),
-        ("tol", c_double), ("warm_start", c_int32),
+        ("tol", c_double), ("warm_start", c_int32), ("use_graph", c_int32),
     ]
+
+
+class segsalsa_image(ctypes.Structure):
+    _fields_ = [("K", c_int32), ("H", c_int32), ("W", c_int32), ("in_offset", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64), ("lambda_", c_double), ("mu", c_double)]
+
+
+class segsalsa_batch_params(ctypes.Structure):
+    _fields_ = [("patch_radius", c_int32), ("patch_weights", POINTER(c_double)), ("schatten_p", c_double),
+                ("iters", c_int32), ("input_is_logits", c_int32), ("residual_every", c_int32), ("tol", c_double),
+                ("warm_start", c_int32), ("use_graph", c_int32)]
 
 
 class segsalsa_stats(ctypes.Structure):
@@ -75,6 +86,12 @@ def lib():
     L.segsalsa_str_state_import.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_size_t, c_void_p,
                                             c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.segsalsa_str_state_import.restype = c_int32
+    L.segsalsa_str_batch_workspace_size.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params),
+                                                    c_int32, POINTER(c_size_t)]
+    L.segsalsa_str_batch_workspace_size.restype = c_int32
+    L.segsalsa_str_solve_batch.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params), c_int32,
+                                           c_void_p, c_void_p, c_void_p, c_size_t, POINTER(segsalsa_stats), c_void_p]
+    L.segsalsa_str_solve_batch.restype = c_int32
     L.segsalsa_profile_enable.argtypes = [c_int32]
     L.segsalsa_profile_enable.restype = c_int32
     L.segsalsa_profile_read.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), c_int32]
@@ -92,19 +109,20 @@ class Problem:
     """Parameters of one SegSALSA-STR problem (mirrors segsalsa_problem)."""
 
     def __init__(self, K, H, W, patch_radius, patch_weights, schatten_p=1.0, lam=1.0, mu=1.0, iters=100,
-                 input_is_logits=False, residual_every=0, tol=0.0, warm_start=False):
+                 input_is_logits=False, residual_every=0, tol=0.0, warm_start=False, use_graph=False):
         self.K, self.H, self.W, self.patch_radius = int(K), int(H), int(W), int(patch_radius)
         self.patch_weights = [float(x) for x in patch_weights]
         self.schatten_p = float(schatten_p)
         self.lam, self.mu, self.iters = float(lam), float(mu), int(iters)
         self.input_is_logits = bool(input_is_logits)
         self.residual_every, self.tol, self.warm_start = int(residual_every), float(tol), bool(warm_start)
+        self.use_graph = bool(use_graph)
 
     def c_struct(self):
         w = (c_double * max(1, len(self.patch_weights)))(*self.patch_weights)
         s = segsalsa_problem(self.K, self.H, self.W, self.patch_radius, ctypes.cast(w, POINTER(c_double)),
                              self.schatten_p, self.lam, self.mu, self.iters, int(self.input_is_logits),
-                             self.residual_every, self.tol, int(self.warm_start))
+                             self.residual_every, self.tol, int(self.warm_start), int(self.use_graph))
         s._keep = w  # keep the weights array alive with the struct
         return s
 
@@ -188,6 +206,59 @@ def segsalsa_str_state_import(problem: Problem, workspace, p_hat, d1, d2, d3, d4
         ctypes.byref(s), _prec(dtype), _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(),
         _dev_ptr(p_hat, "p_hat", dtype, nel), _dev_ptr(d1, "d1", dtype, nel), _dev_ptr(d2, "d2", dtype, 2 * L * nel),
         _dev_ptr(d3, "d3", dtype, nel), _dev_ptr(d4, "d4", dtype, nel), _stream(stream)))
+
+
+class BatchParams:
+    """Parameters shared by the images of a batch (mirrors segsalsa_batch_params)."""
+
+    def __init__(self, patch_radius, patch_weights, schatten_p=1.0, iters=100, input_is_logits=False,
+                 residual_every=0, tol=0.0, warm_start=False, use_graph=False):
+        self.patch_radius = int(patch_radius)
+        self.patch_weights = [float(x) for x in patch_weights]
+        self.schatten_p, self.iters = float(schatten_p), int(iters)
+        self.input_is_logits, self.residual_every, self.tol = bool(input_is_logits), int(residual_every), float(tol)
+        self.warm_start, self.use_graph = bool(warm_start), bool(use_graph)
+
+    def c_struct(self):
+        w = (c_double * max(1, len(self.patch_weights)))(*self.patch_weights)
+        s = segsalsa_batch_params(self.patch_radius, ctypes.cast(w, POINTER(c_double)), self.schatten_p, self.iters,
+                                  int(self.input_is_logits), self.residual_every, self.tol, int(self.warm_start),
+                                  int(self.use_graph))
+        s._keep = w
+        return s
+
+
+def image_table(shapes, lams, mus):
+    """segsalsa_image array for [K][H][W] images packed back to back (same layout in and out)."""
+    arr = (segsalsa_image * len(shapes))()
+    off = 0
+    for i, ((K, H, W), lam, mu) in enumerate(zip(shapes, lams, mus)):
+        arr[i] = segsalsa_image(K, H, W, off, off, lam, mu)
+        off += K * H * W
+    return arr, off
+
+
+def segsalsa_str_batch_workspace_size(images, params: BatchParams, precision: int) -> int:
+    n = c_size_t(0)
+    s = params.c_struct()
+    _check(lib().segsalsa_str_batch_workspace_size(len(images), images, ctypes.byref(s), int(precision),
+                                                   ctypes.byref(n)))
+    return int(n.value)
+
+
+def segsalsa_str_solve_batch(images, params: BatchParams, inp, z_out, workspace, stats: bool = False, stream=None):
+    """Solve all images of the packed batch; returns a list of stats dicts if stats=True (then waits)."""
+    prec = _prec(z_out.dtype)
+    s = params.c_struct()
+    st = (segsalsa_stats * len(images))() if stats else None
+    _check(lib().segsalsa_str_solve_batch(len(images), images, ctypes.byref(s), prec,
+                                          _dev_ptr(inp, "input", z_out.dtype) if inp is not None else None,
+                                          _dev_ptr(z_out, "z_out"), _dev_ptr(workspace, "workspace", torch.uint8),
+                                          workspace.numel(), st, _stream(stream)))
+    if st is None:
+        return None
+    return [dict(primal_res=x.primal_res, dual_res=x.dual_res, objective=x.objective, rounds_done=x.rounds_done,
+                 flags=x.flags) for x in st]
 
 
 PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "reserved")
