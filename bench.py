@@ -63,9 +63,9 @@ def load_traffic(workload: str, dtype: str, src_hash: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def time_solves(S, torch, pr, x, z, ws, steps, warmup):
+def time_calls(torch, call, steps, warmup):
     for _ in range(warmup):
-        S.segsalsa_str_solve(pr, x, z, ws)
+        call()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -73,11 +73,24 @@ def time_solves(S, torch, pr, x, z, ws, steps, warmup):
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
-        S.segsalsa_str_solve(pr, x, z, ws)
+        call()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3
+
+
+def phase_times(S, torch, call, steps):
+    """Average per-launch GPU time of each phase, from HIP events recorded around every launch."""
+    S.segsalsa_profile_read(reset=True)
+    S.segsalsa_profile_enable(True)
+    for _ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    S.segsalsa_profile_enable(False)
+    tot = S.segsalsa_profile_read(reset=True)
+    return {name: dict(avg_us=1e3 * tot[name][0] / max(1, tot[name][1]), launches=tot[name][1])
+            for name in S.PHASES[:4]}
 
 
 def cpu_baseline(wl, probs, weights, budget_s: float):
@@ -99,6 +112,56 @@ def cpu_baseline(wl, probs, weights, budget_s: float):
                        f"1 thread (BLAS/FFT limited to 1), {dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
 
 
+def bench_batch(S, torch, synth, args):
+    """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one graph launch per step."""
+    B = synth.BATCH
+    shapes = synth.batch_shapes()
+    probs = [t[0] for t in synth.make_batch(shapes)]
+    c = synth.gaussian_patch_multipliers(B["M"], B["patch_sigma"])
+    imgs, total = S.image_table([(K, H, W) for (H, W, K) in shapes], [B["lam"]] * len(shapes),
+                                [B["mu"]] * len(shapes))
+    units = sum(H * W * K for (H, W, K) in shapes) * B["iters"]
+    L = (2 * B["M"] + 1) ** 2
+    out, zs = {}, {}
+    for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        if args.fp32_only and tag == "f64":
+            continue
+        packed = torch.cat([torch.from_numpy(x).reshape(-1) for x in probs]).to(device="cuda", dtype=dtype)
+        z = torch.empty_like(packed)
+        params = S.BatchParams(B["M"], c, 1.0, B["iters"], use_graph=not args.no_graph)
+        ws = torch.empty(S.segsalsa_str_batch_workspace_size(imgs, params, S._prec(dtype)), dtype=torch.uint8,
+                         device="cuda")
+        log(f"[bench] batch {tag}")
+        ms, _ = time_calls(torch, lambda: S.segsalsa_str_solve_batch(imgs, params, packed, z, ws), args.steps,
+                           args.warmup)
+        direct = S.BatchParams(B["M"], c, 1.0, B["iters"])
+        ph = phase_times(S, torch, lambda: S.segsalsa_str_solve_batch(imgs, direct, packed, z, ws), args.steps)
+        zs[tag] = z.double()
+        out[tag] = dict(ms_per_step=ms, value=units / (ms * 1e-3), phases=ph)
+        log(f"[bench] batch {tag}: {ms:.2f} ms/step {units / (ms * 1e-3):.4g} units/s {ph}")
+        del ws, packed
+        torch.cuda.empty_cache()
+    z_err = float(torch.max(torch.abs(zs["f32"] - zs["f64"])).item()) if "f64" in zs else None
+    prox = out["f32"]["phases"]["prox_rhs"]
+    bytes_launch = sum(H * W * K for (H, W, K) in shapes) * prox_bytes_per_unit(L, 4)
+    achieved = bytes_launch / (prox["avg_us"] * 1e-6) / 1e9
+    res = {"metric": METRIC, "value": out["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0,
+           "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": out["f32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": B["name"], "images": len(shapes), "pixels": sum(H * W for H, W, _ in shapes),
+                      "patch": "3x3", "rounds": B["iters"]},
+           "roofline": {"bound": "hbm", "kernel": "prox_rhs (all groups)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "bytes_per_launch_alg": bytes_launch, "avg_launch_us": prox["avg_us"]},
+           "z_err_fp32_vs_fp64": z_err,
+           "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in out["f32"]["phases"].items()}}
+    if "f64" in out:
+        res["fp64"] = {"value": out["f64"]["value"], "ms_per_step": out["f64"]["ms_per_step"]}
+        res["speedup_fp32_vs_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +172,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
+    ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of one graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 512 MiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -135,6 +199,10 @@ def main():
         log("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written")
         del src, dst
 
+    if args.workload == synth.BATCH["name"]:
+        print(json.dumps(bench_batch(S, torch, synth, args)), flush=True)
+        return
+
     wl = synth.WORKLOADS[args.workload]
     if args.schatten_p is not None:
         import dataclasses
@@ -147,22 +215,16 @@ def main():
         if args.fp32_only and tag == "f64":
             continue
         x = torch.from_numpy(d["probs"]).to(device="cuda", dtype=dtype)
-        pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters)
+        pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters,
+                       use_graph=not args.no_graph)
         ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
         z = torch.empty_like(x)
-        log(f"[bench] {wl.name} {tag}: warmup {args.warmup}, steps {args.steps}")
-        ms_gpu, ms_wall = time_solves(S, torch, pr, x, z, ws, args.steps, args.warmup)
+        log(f"[bench] {wl.name} {tag}: warmup {args.warmup}, steps {args.steps}, graph {not args.no_graph}")
+        ms_gpu, ms_wall = time_calls(torch, lambda: S.segsalsa_str_solve(pr, x, z, ws), args.steps, args.warmup)
         zs[tag] = z.double().cpu().numpy()
-        # per-kernel durations: a second pass over the same steps with HIP events around each launch
-        S.segsalsa_profile_read(reset=True)
-        S.segsalsa_profile_enable(True)
-        for _ in range(args.steps):
-            S.segsalsa_str_solve(pr, x, z, ws)
-        torch.cuda.synchronize()
-        S.segsalsa_profile_enable(False)
-        tot = S.segsalsa_profile_read(reset=True)
-        phases = {name: dict(avg_us=1e3 * tot[name][0] / max(1, tot[name][1]), launches=tot[name][1])
-                  for name in S.PHASES[:4]}
+        # per-kernel durations: a second pass over the same steps, direct launches with HIP events around each
+        pr_direct = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters)
+        phases = phase_times(S, torch, lambda: S.segsalsa_str_solve(pr_direct, x, z, ws), args.steps)
         res[tag] = dict(ms_per_step=ms_gpu, ms_wall=ms_wall, value=units / (ms_gpu * 1e-3), phases=phases)
         log(f"[bench] {tag}: {ms_gpu:.3f} ms/step, {units / (ms_gpu * 1e-3):.4g} units/s, phases {phases}")
         del ws, x, z

@@ -41,10 +41,9 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Dynamic LDS one workgroup may use (gfx950 has 160 KiB per CU).
 constexpr size_t kLdsBudget = 160 * 1024;
 
-FftPlanDev make_fft_plan(int N) {
-  FftPlanDev p;
-  std::memset(&p, 0, sizeof(p));
-  p.N = N;
+// Factor a length into radices: 8s, then 4 and 2, 3s, 5s, then the other
+// primes in increasing order.
+int factorize(int N, int* rad) {
   std::vector<int> r;
   int n = N;
   while (n % 8 == 0) { r.push_back(8); n /= 8; }
@@ -55,8 +54,35 @@ FftPlanDev make_fft_plan(int N) {
   for (int f = 7; (long long)f * f <= n; f += 2)
     while (n % f == 0) { r.push_back(f); n /= f; }
   if (n > 1) r.push_back(n);
-  p.nst = (int)r.size();
-  for (int i = 0; i < p.nst; ++i) p.rad[i] = r[i];
+  for (size_t i = 0; i < r.size(); ++i) rad[i] = r[i];
+  return (int)r.size();
+}
+
+// Largest prime factor handled by a direct DFT stage; longer primes go
+// through Bluestein (SEGSALSA_BLUESTEIN_PRIME overrides, for tuning).
+int bluestein_prime() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("SEGSALSA_BLUESTEIN_PRIME");
+    v = e ? std::max(5, std::atoi(e)) : 40;
+  }
+  return v;
+}
+
+FftPlanDev make_fft_plan(int N) {
+  FftPlanDev p;
+  std::memset(&p, 0, sizeof(p));
+  p.N = N;
+  p.nst = factorize(N, p.rad);
+  int big = 1;
+  for (int i = 0; i < p.nst; ++i) big = std::max(big, p.rad[i]);
+  if (big > bluestein_prime() && big != 8) {
+    int M = 1;
+    while (M < 2 * N - 1) M *= 2;
+    p.blu = 1;
+    p.M = M;
+    p.mnst = factorize(M, p.mrad);
+  }
   return p;
 }
 
@@ -74,7 +100,7 @@ struct Plan {
   size_t col_lds;
   // workspace offsets (bytes)
   size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_frow, off_fcol, off_phat, off_dm, off_d2, off_acc, off_spec,
-      off_zprev, off_restile, off_partial, off_out, total;
+      off_zprev, off_restile, off_partial, off_out, off_chW, off_chH, off_bfW, off_bfH, off_twMW, off_twMH, total;
   int npartial;
 };
 
@@ -273,20 +299,27 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   // thread for latency hiding, whole rows (columns) plus the twiddle table in
   // LDS; column blocks of 8+ columns on tall images for coalesced rows.
   const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
+  // Bluestein needs scratch next to the data; where that exceeds LDS, keep
+  // the direct stages
+  if (p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
+  if (p.fcol.blu && ((size_t)H + p.fcol.M) * cs > kLdsBudget) p.fcol.blu = 0;
   {
-    long long rpb = std::max<long long>(1, 512 / W);
+    const int Lr = p.frow.blu ? p.frow.M : W;      // elements per row inside the transform
+    long long rpb = std::max<long long>(1, 512 / Lr);
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
     p.rows_per_block = (int)rpb;
-    fft_threads(rpb * W, p.row_ept, p.row_threads);
-    p.row_lds = (size_t)(rpb + 1) * W * cs;
+    fft_threads(rpb * Lr, p.row_ept, p.row_threads);
+    p.row_lds = ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
   }
   {
+    const int Lc = p.fcol.blu ? p.fcol.M : H;
     int cb = 1;
-    while (cb < 64 && cb * 2 <= W && (long long)(cb * 2) * H <= cap && ((long long)(cb * 2) * H <= 1024 || cb * 2 <= 8))
+    while (cb < 64 && cb * 2 <= W && (long long)(cb * 2) * Lc <= cap &&
+           ((long long)(cb * 2) * Lc <= 1024 || cb * 2 <= 8))
       cb *= 2;
     p.cols_per_block = cb;
-    fft_threads((long long)cb * H, p.col_ept, p.col_threads);
-    p.col_lds = (size_t)(cb + 1) * H * cs;
+    fft_threads((long long)cb * Lc, p.col_ept, p.col_threads);
+    p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
   }
   const size_t nt = (size_t)p.g.ntiles();
   size_t off = 0;
@@ -308,6 +341,13 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   p.npartial = std::max<int>(kDiagBlocks, (int)(((size_t)H * W + 255) / 256));
   p.off_partial = off; off = align_up(off + (size_t)p.npartial * 8);
   p.off_out = off; off = align_up(off + 4 * 8);
+  // Bluestein tables (only for lengths that use it)
+  p.off_chW = off; off = align_up(off + (p.frow.blu ? (size_t)W * cs : 0));
+  p.off_chH = off; off = align_up(off + (p.fcol.blu ? (size_t)H * cs : 0));
+  p.off_bfW = off; off = align_up(off + (size_t)p.frow.M * cs);
+  p.off_bfH = off; off = align_up(off + (size_t)p.fcol.M * cs);
+  p.off_twMW = off; off = align_up(off + (size_t)p.frow.M * cs);
+  p.off_twMH = off; off = align_up(off + (size_t)p.fcol.M * cs);
   p.total = off;
   if (const char* lg = std::getenv("SEGSALSA_LOG")) {
     if (lg[0] == '1')
@@ -447,6 +487,26 @@ struct LaunchSet {
 };
 
 template <typename T>
+FftTab<T> row_tab(const Plan& p, void* base) {
+  FftTab<T> t;
+  t.tw = wsp<C2<T>>(base, p.off_twW);
+  t.chirp = wsp<C2<T>>(base, p.off_chW);
+  t.bf = wsp<C2<T>>(base, p.off_bfW);
+  t.twM = wsp<C2<T>>(base, p.off_twMW);
+  return t;
+}
+
+template <typename T>
+FftTab<T> col_tab(const Plan& p, void* base) {
+  FftTab<T> t;
+  t.tw = wsp<C2<T>>(base, p.off_twH);
+  t.chirp = wsp<C2<T>>(base, p.off_chH);
+  t.bf = wsp<C2<T>>(base, p.off_bfH);
+  t.twM = wsp<C2<T>>(base, p.off_twMH);
+  return t;
+}
+
+template <typename T>
 hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& active, void* const* zs,
                          const void* const* ins, LaunchSet& ls, hipStream_t st) {
   (void)ins;
@@ -523,7 +583,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     f.frow = wsp<int>(base, p.off_frow);
     f.fcol = wsp<int>(base, p.off_fcol);
     f.spec = wsp<C2<T>>(base, p.off_spec);
-    f.tw = wsp<C2<T>>(base, p.off_twW);
+    f.tab = row_tab<T>(p, base);
     f.plan = p.frow;
     ColArgs<T>& k = ca[q];
     std::memset(&k, 0, sizeof(k));
@@ -531,7 +591,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     k.H = p.H; k.W = p.W; k.P = p.P;
     k.cols_per_block = p.cols_per_block;
     k.spec = f.spec;
-    k.tw = wsp<C2<T>>(base, p.off_twH);
+    k.tab = col_tab<T>(p, base);
     k.sx = wsp<double>(base, p.off_sx);
     k.sy = wsp<double>(base, p.off_sy);
     k.wsum = wsum;
@@ -544,11 +604,12 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     v.rows_per_block = p.rows_per_block;
     v.spec = f.spec;
     v.z = reinterpret_cast<T*>(zs[active[q]]);
-    v.tw = f.tw;
+    v.tab = f.tab;
     v.plan = p.frow;
     rb += p.P * ceil_div(p.H, p.rows_per_block);
     cb += p.P * ceil_div(p.W, p.cols_per_block);
-    const long long ritems = (long long)p.rows_per_block * p.W, citems = (long long)p.cols_per_block * p.H;
+    const long long ritems = (long long)p.rows_per_block * (p.frow.blu ? p.frow.M : p.W);
+    const long long citems = (long long)p.cols_per_block * (p.fcol.blu ? p.fcol.M : p.H);
     ls.row_threads = std::max<int>(ls.row_threads, (int)((ritems + ls.row_ept - 1) / ls.row_ept));
     ls.col_threads = std::max<int>(ls.col_threads, (int)((citems + ls.col_ept - 1) / ls.col_ept));
     ls.row_lds = std::max(ls.row_lds, p.row_lds);
@@ -643,7 +704,21 @@ hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* 
     sa.twH = wsp<C2<T>>(base, p.off_twH);
     sa.sx = wsp<double>(base, p.off_sx);
     sa.sy = wsp<double>(base, p.off_sy);
+    sa.MW = p.frow.blu ? p.frow.M : 0;
+    sa.MH = p.fcol.blu ? p.fcol.M : 0;
+    sa.chW = wsp<C2<T>>(base, p.off_chW);
+    sa.chH = wsp<C2<T>>(base, p.off_chH);
+    sa.twMW = wsp<C2<T>>(base, p.off_twMW);
+    sa.twMH = wsp<C2<T>>(base, p.off_twMH);
     if ((e = launch_setup(sa, st)) != hipSuccess) return e;
+    if (p.frow.blu) {
+      const FftTab<T> t = row_tab<T>(p, base);
+      if ((e = launch_bluestein_table(p.frow, t, wsp<C2<T>>(base, p.off_bfW), st)) != hipSuccess) return e;
+    }
+    if (p.fcol.blu) {
+      const FftTab<T> t = col_tab<T>(p, base);
+      if ((e = launch_bluestein_table(p.fcol, t, wsp<C2<T>>(base, p.off_bfH), st)) != hipSuccess) return e;
+    }
     if (!c.warm) {
       if ((e = launch_fill_zero(wsp<char>(base, p.off_flags), 64, st)) != hipSuccess) return e;
       if ((e = launch_fill_zero(wsp<char>(base, p.off_d2), p.off_acc - p.off_d2, st)) != hipSuccess) return e;

@@ -141,7 +141,16 @@ __device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>
     const int item = threadIdx.x + it * blockDim.x;
     ob[it] = -1;
     if (item < total) {
-      const int b = item / NR, j = item - b * NR;
+      // interleaved transforms (bs == 1): consecutive lanes take consecutive transforms,
+      // so one instruction touches one contiguous run of LDS words
+      int b, j;
+      if (bs == 1) {
+        j = item / nb;
+        b = item - j * nb;
+      } else {
+        b = item / NR;
+        j = item - b * NR;
+      }
       const int k = j % Ns;
       const int base = b * bs;
 #pragma unroll
@@ -179,7 +188,14 @@ __device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, 
     const int item = threadIdx.x + it * blockDim.x;
     oi[it] = -1;
     if (item < total) {
-      const int b = item / N, rem = item - b * N;
+      int b, rem;
+      if (bs == 1) {
+        rem = item / nb;
+        b = item - rem * nb;
+      } else {
+        b = item / N;
+        rem = item - b * N;
+      }
       const int j = rem / R, q = rem - j * R;
       const int k = j % Ns;
       const int base = b * bs;
@@ -206,23 +222,120 @@ __device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, 
   __syncthreads();
 }
 
-// Unnormalised DFT (inv = false: exp(-2 pi i ...); inv = true: exp(+2 pi i ...)).
-// The workgroup must hold at least nb * N / EPT threads.
+template <typename T>
+__device__ inline C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// Mixed-radix Stockham DFT over the given factors (unnormalised).
 template <typename T, int EPT>
-__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw, bool inv) {
+__device__ void stockham(C2<T>* buf, int N, int nst, const int* rad, int nb, int es, int bs, const C2<T>* tw,
+                         bool inv) {
   int Ns = 1;
-  for (int s = 0; s < p.nst; ++s) {
-    const int R = p.rad[s];
+  for (int s = 0; s < nst; ++s) {
+    const int R = rad[s];
     switch (R) {
-      case 2: stage_reg<T, 2, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 3: stage_reg<T, 3, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 4: stage_reg<T, 4, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 5: stage_reg<T, 5, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      case 8: stage_reg<T, 8, EPT>(buf, p.N, nb, es, bs, tw, Ns, inv); break;
-      default: stage_generic<T, EPT>(buf, p.N, R, nb, es, bs, tw, Ns, inv); break;
+      case 2: stage_reg<T, 2, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+      case 3: stage_reg<T, 3, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+      case 4: stage_reg<T, 4, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+      case 5: stage_reg<T, 5, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+      case 8: stage_reg<T, 8, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+      default: stage_generic<T, EPT>(buf, N, R, nb, es, bs, tw, Ns, inv); break;
     }
     Ns *= R;
   }
+}
+
+// Unnormalised DFT of nb transforms of length p.N in LDS (inv = false:
+// exp(-2 pi i ...); inv = true: exp(+2 pi i ...)).  Element i of transform b
+// is at buf[b * bs + i * es].  tw: the N twiddles in LDS (Stockham path).
+// Bluestein path: X_k = c_k sum_n (x_n c_n) d_(k-n) with c_n = exp(-i pi n^2 / N)
+// and d = conj(c), the sum a length-M cyclic convolution by FFT; scr holds
+// nb * M elements of LDS scratch.  The workgroup must hold at least
+// nb * max(N, M) / EPT threads.
+template <typename T, int EPT>
+__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw,
+                        const FftTab<T>& tab, C2<T>* scr, bool inv) {
+  if (!p.blu) {
+    stockham<T, EPT>(buf, p.N, p.nst, p.rad, nb, es, bs, tw, inv);
+    return;
+  }
+  const int N = p.N, M = p.M;
+  for (int idx = threadIdx.x; idx < nb * M; idx += blockDim.x) {
+    const int b = idx / M, n = idx - b * M;
+    C2<T> v = {T(0), T(0)};
+    if (n < N) {
+      C2<T> c = tab.chirp[n];
+      if (inv) c.y = -c.y;
+      v = cmul(buf[b * bs + n * es], c);
+    }
+    scr[idx] = v;
+  }
+  __syncthreads();
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, false);
+  for (int idx = threadIdx.x; idx < nb * M; idx += blockDim.x) {
+    const int m = idx & (M - 1);
+    C2<T> w;
+    if (inv) {  // DFT of conj(d) is conj(DFT(d)) read at -m
+      w = tab.bf[(M - m) & (M - 1)];
+      w.y = -w.y;
+    } else {
+      w = tab.bf[m];
+    }
+    scr[idx] = cmul(scr[idx], w);
+  }
+  __syncthreads();
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, true);
+  const T invM = T(1) / T(M);
+  for (int idx = threadIdx.x; idx < nb * N; idx += blockDim.x) {
+    const int b = idx / N, k = idx - b * N;
+    C2<T> c = tab.chirp[k];
+    if (inv) c.y = -c.y;
+    buf[b * bs + k * es] = cscale(cmul(scr[b * M + k], c), invM);
+  }
+  __syncthreads();
+}
+
+// Kernel DFT of the Bluestein convolution: bf = DFT_M(d), d_m = exp(+i pi m^2 / N)
+// for m < N and at M - m, zero elsewhere (one workgroup, M elements in LDS).
+template <typename T>
+__global__ void __launch_bounds__(1024) bluestein_table_kernel(FftPlanDev p, FftTab<T> tab, C2<T>* bf_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  const int N = p.N, M = p.M;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    C2<T> v = {T(0), T(0)};
+    const int j = m < N ? m : (M - m < N ? M - m : -1);
+    if (j >= 0) {
+      v = tab.chirp[j];
+      v.y = -v.y;
+    }
+    buf[m] = v;
+  }
+  __syncthreads();
+  stockham<T, kFftEptMax>(buf, M, p.mnst, p.mrad, 1, 1, M, tab.twM, false);
+  for (int m = threadIdx.x; m < M; m += blockDim.x) bf_out[m] = buf[m];
+}
+
+template <typename T>
+hipError_t launch_bluestein_table_t(const FftPlanDev& p, const FftTab<T>& tab, C2<T>* bf_out, hipStream_t st) {
+  auto fn = bluestein_table_kernel<T>;
+  static bool lds_set = false;
+  if (!lds_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
+    if (e != hipSuccess) return e;
+    lds_set = true;
+  }
+  const int threads = p.M / kFftEptMax < 64 ? 64 : (p.M / kFftEptMax > 1024 ? 1024 : p.M / kFftEptMax);
+  hipLaunchKernelGGL(fn, dim3(1), dim3(threads), (size_t)p.M * sizeof(C2<T>), st, p, tab, bf_out);
+  return hipGetLastError();
+}
+hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<float>& tab, C2<float>* bf, hipStream_t st) {
+  return launch_bluestein_table_t(p, tab, bf, st);
+}
+hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab, C2<double>* bf, hipStream_t st) {
+  return launch_bluestein_table_t(p, tab, bf, st);
 }
 
 template <typename T, int EPT>
@@ -237,8 +350,9 @@ __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
-  C2<T>* tw = buf + a.rows_per_block * W;
-  for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tw[t];
+  C2<T>* tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
+  if (!a.plan.blu)
+    for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tab.tw[t];
   // right-hand side = sum of the grown-tile partial sums covering (r, c)
   const size_t plane = (size_t)a.g.ER * a.g.EC;
   const bool has1 = k1 < a.K;
@@ -262,7 +376,7 @@ __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T>*
     buf[idx] = C2<T>{s0, s1};
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, false);
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, false);
   C2<T>* out = a.spec + ((size_t)m * H + row0) * W;
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) out[idx] = buf[idx];
 }
@@ -280,21 +394,22 @@ __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T>* __rest
   const int col0 = (bid - m * ncb) * CB;
   const int nb = min(CB, W - col0);
   C2<T>* sp = a.spec + (size_t)m * H * W + col0;
-  C2<T>* tw = buf + CB * H;
-  for (int t = threadIdx.x; t < H; t += blockDim.x) tw[t] = a.tw[t];
+  C2<T>* tw = buf + CB * H;  // twiddles, or Bluestein scratch
+  if (!a.plan.blu)
+    for (int t = threadIdx.x; t < H; t += blockDim.x) tw[t] = a.tab.tw[t];
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
     buf[idx] = sp[(size_t)y * W + j];
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, false);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, a.tab, tw, false);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
     const T inv = T(a.scale) / (T(3) + T(a.wsum) * T(a.sx[col0 + j] + a.sy[y]));
     buf[idx] = cscale(buf[idx], inv);
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, a.tab, tw, true);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
     sp[(size_t)y * W + j] = buf[idx];
@@ -313,11 +428,12 @@ __global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T>*
   const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const C2<T>* in = a.spec + ((size_t)m * H + row0) * W;
-  C2<T>* tw = buf + a.rows_per_block * W;
-  for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tw[t];
+  C2<T>* tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
+  if (!a.plan.blu)
+    for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tab.tw[t];
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) buf[idx] = in[idx];
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, true);
   const int k0 = 2 * m, k1 = 2 * m + 1;
   T* z0 = a.z + ((size_t)k0 * H + row0) * W;
   T* z1 = a.z + ((size_t)k1 * H + row0) * W;

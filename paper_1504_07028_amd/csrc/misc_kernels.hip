@@ -23,6 +23,27 @@ __global__ void setup_kernel(const SetupArgs<T> a) {
     const double h = sinpi((double)t / (double)a.H);
     a.sy[t] = 4.0 * h * h;
   }
+  // Bluestein chirps, angle pi (t^2 mod 2N) / N, and power-of-two twiddles
+  if (a.MW && t < a.W) {
+    double s, c;
+    sincospi((double)(((long long)t * t) % (2LL * a.W)) / (double)a.W, &s, &c);
+    a.chW[t] = C2<T>{T(c), T(-s)};
+  }
+  if (a.MH && t < a.H) {
+    double s, c;
+    sincospi((double)(((long long)t * t) % (2LL * a.H)) / (double)a.H, &s, &c);
+    a.chH[t] = C2<T>{T(c), T(-s)};
+  }
+  if (t < a.MW) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)a.MW, &s, &c);
+    a.twMW[t] = C2<T>{T(c), T(-s)};
+  }
+  if (t < a.MH) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)a.MH, &s, &c);
+    a.twMH[t] = C2<T>{T(c), T(-s)};
+  }
   // fold lists (the host checked that none overflows)
   if (t < a.H) {
     int* o = a.frow + (size_t)t * kFoldStride;
@@ -36,7 +57,9 @@ __global__ void setup_kernel(const SetupArgs<T> a) {
 
 template <typename T>
 hipError_t launch_setup_t(const SetupArgs<T>& a, hipStream_t st) {
-  const int n = a.W > a.H ? a.W : a.H;
+  int n = a.W > a.H ? a.W : a.H;
+  n = n > a.MW ? n : a.MW;
+  n = n > a.MH ? n : a.MH;
   hipLaunchKernelGGL(setup_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -125,10 +125,27 @@ struct ProxArgs {
   T c[kMaxL];
 };
 
+// One 1-D DFT length.  Mixed-radix Stockham over the factors in rad[], or,
+// for lengths with a large prime factor (blu = 1), Bluestein's chirp
+// transform: a length-M cyclic convolution (M a power of two >= 2N - 1)
+// computed with the power-of-two radices in mrad[].
 struct FftPlanDev {
   int N;
   int nst;
   int rad[kMaxRadices];
+  int blu;
+  int M;
+  int mnst;
+  int mrad[kMaxRadices];
+};
+
+// Tables of one DFT length (device memory).
+template <typename T>
+struct FftTab {
+  const C2<T>* tw;     // N twiddles exp(-2 pi i t / N) (Stockham path)
+  const C2<T>* chirp;  // N values exp(-i pi n^2 / N) (Bluestein)
+  const C2<T>* bf;     // M values: DFT_M of the kernel exp(+i pi m^2 / N) wrapped cyclically (Bluestein)
+  const C2<T>* twM;    // M twiddles exp(-2 pi i t / M) (Bluestein)
 };
 
 template <typename T>
@@ -141,7 +158,7 @@ struct RowFwdArgs {
   const int* __restrict__ frow; // [H][kFoldStride] fold lists of rows
   const int* __restrict__ fcol; // [W][kFoldStride] fold lists of columns
   C2<T>* __restrict__ spec;     // [P][H][W]
-  const C2<T>* __restrict__ tw; // W twiddles exp(-2 pi i t / W)
+  FftTab<T> tab;                // row-length tables
   FftPlanDev plan;
 };
 
@@ -151,7 +168,7 @@ struct ColArgs {
   int H, W, P;
   int cols_per_block;
   C2<T>* __restrict__ spec;
-  const C2<T>* __restrict__ tw;   // H twiddles
+  FftTab<T> tab;                  // column-length tables
   const double* __restrict__ sx;  // 4 sin^2(pi kx / W)
   const double* __restrict__ sy;  // 4 sin^2(pi ky / H)
   double wsum;                    // sum_j c_j^2
@@ -166,7 +183,7 @@ struct RowInvArgs {
   int rows_per_block;
   const C2<T>* __restrict__ spec;
   T* __restrict__ z;
-  const C2<T>* __restrict__ tw;
+  FftTab<T> tab;
   FftPlanDev plan;
 };
 

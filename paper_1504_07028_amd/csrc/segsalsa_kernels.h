@@ -60,7 +60,14 @@ struct SetupArgs {
   C2<T>* twH;   // exp(-2 pi i t / H), t < H
   double* sx;   // 4 sin^2(pi t / W)
   double* sy;   // 4 sin^2(pi t / H)
+  int MW, MH;   // Bluestein convolution lengths (0: not used)
+  C2<T>* chW;   // exp(-i pi t^2 / W), t < W (Bluestein)
+  C2<T>* chH;
+  C2<T>* twMW;  // exp(-2 pi i t / MW), t < MW
+  C2<T>* twMH;
 };
+hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<float>& tab, C2<float>* bf, hipStream_t st);
+hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab, C2<double>* bf, hipStream_t st);
 hipError_t launch_setup(const SetupArgs<float>& a, hipStream_t st);
 hipError_t launch_setup(const SetupArgs<double>& a, hipStream_t st);
 
