@@ -186,10 +186,10 @@ bool choose_tiles(Plan& p) {
 // that keep the workgroup within 1024 threads.
 void fft_threads(long long items, int& ept, int& threads) {
   ept = 2;
-  while (ept < kFftEptMax && (items + ept - 1) / ept > 1024) ept *= 2;
+  while (ept < kFftEptMax && (items + ept - 1) / ept > kFftMaxThreads) ept *= 2;
   long long t = (items + ept - 1) / ept;
   t = (t + 63) / 64 * 64;
-  threads = (int)std::max<long long>(64, std::min<long long>(t, 1024));
+  threads = (int)std::max<long long>(64, std::min<long long>(t, kFftMaxThreads));
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +305,7 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   if (p.fcol.blu && ((size_t)H + p.fcol.M) * cs > kLdsBudget) p.fcol.blu = 0;
   {
     const int Lr = p.frow.blu ? p.frow.M : W;      // elements per row inside the transform
-    long long rpb = std::max<long long>(1, 512 / Lr);
+    long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
     p.rows_per_block = (int)rpb;
     fft_threads(rpb * Lr, p.row_ept, p.row_threads);
@@ -615,8 +615,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     ls.row_lds = std::max(ls.row_lds, p.row_lds);
     ls.col_lds = std::max(ls.col_lds, p.col_lds);
   }
-  ls.row_threads = std::min(1024, (ls.row_threads + 63) / 64 * 64);
-  ls.col_threads = std::min(1024, (ls.col_threads + 63) / 64 * 64);
+  ls.row_threads = std::min(kFftMaxThreads, (ls.row_threads + 63) / 64 * 64);
+  ls.col_threads = std::min(kFftMaxThreads, (ls.col_threads + 63) / 64 * 64);
   ls.row_blocks = rb;
   ls.col_blocks = cb;
   hipError_t e;

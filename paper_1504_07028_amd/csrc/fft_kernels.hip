@@ -123,11 +123,57 @@ struct Bfly<T, 8> {
   }
 };
 
+// DFT of an odd prime number P of values in registers, using the pairs
+// (r, P - r): y_q = a_q + sg i b_q and y_(P-q) = a_q - sg i b_q with
+// a_q = v_0 + sum_r (v_r + v_(P-r)) cos(2 pi r q / P) and
+// b_q = sum_r (v_r - v_(P-r)) sin(2 pi r q / P), r = 1 .. (P-1)/2.
+// cos and sin come from the length-N twiddle table in global memory
+// (entry m N / P = exp(-2 pi i m / P)); the index is wavefront-uniform.
+template <typename T, int P>
+struct BflyOdd {
+  __device__ __forceinline__ static void run(C2<T>* v, T sg, const C2<T>* __restrict__ gtw, int stride) {
+    constexpr int Hh = (P - 1) / 2;
+    C2<T> sm[Hh], df[Hh];
+    C2<T> y0 = v[0];
+#pragma unroll
+    for (int r = 1; r <= Hh; ++r) {
+      sm[r - 1] = cadd(v[r], v[P - r]);
+      df[r - 1] = csub(v[r], v[P - r]);
+      y0 = cadd(y0, sm[r - 1]);
+    }
+#pragma unroll
+    for (int q = 1; q <= Hh; ++q) {
+      C2<T> a = v[0], b = {T(0), T(0)};
+#pragma unroll
+      for (int r = 1; r <= Hh; ++r) {
+        const C2<T> w = gtw[((r * q) % P) * stride];
+        const T c = w.x, sn = -w.y;
+        a.x += sm[r - 1].x * c;
+        a.y += sm[r - 1].y * c;
+        b.x += df[r - 1].x * sn;
+        b.y += df[r - 1].y * sn;
+      }
+      const C2<T> e = cmuli(b, sg);
+      v[q] = cadd(a, e);
+      v[P - q] = csub(a, e);
+    }
+    v[0] = y0;
+  }
+};
+
+// Odd primes with a register butterfly; larger primes take the direct LDS
+// stage (their register butterflies cost more occupancy than they save, as
+// measured on the 145-point transforms) or Bluestein.
+template <typename T>
+__host__ __device__ constexpr bool is_odd_prime_radix(int R) {
+  return R == 7 || R == 11 || R == 13;
+}
+
 // One Stockham stage with a register butterfly of radix R, in place in LDS.
 // nb transforms of length N; element i of transform b sits at b*bs + i*es.
 // Ns is the product of the radices of the previous stages.
 template <typename T, int R, int EPT>
-__device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* tw, int Ns,
+__device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* tw, const C2<T>* gtw, int Ns,
                           bool inv) {
   constexpr int IT = (EPT + R - 1) / R;
   const T sg = inv ? T(1) : T(-1);
@@ -159,7 +205,10 @@ __device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>
 #pragma unroll
         for (int r = 1; r < R; ++r) v[it][r] = twmul(v[it][r], tw[k * r * stw], inv);
       }
-      Bfly<T, R>::run(v[it], sg);
+      if constexpr (is_odd_prime_radix<T>(R))
+        BflyOdd<T, R>::run(v[it], sg, gtw, N / R);
+      else
+        Bfly<T, R>::run(v[it], sg);
       ob[it] = base + ((j - k) * R + k) * es;
     }
   }
@@ -176,7 +225,7 @@ __device__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>
 
 // Stockham stage of any radix R as a direct DFT: one output per work item.
 template <typename T, int EPT>
-__device__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
+__device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
                               int Ns, bool inv) {
   const int NR = N / R;
   const int total = nb * N;
@@ -229,17 +278,28 @@ __device__ inline C2<T> cmul(C2<T> a, C2<T> b) {
 
 // Mixed-radix Stockham DFT over the given factors (unnormalised).
 template <typename T, int EPT>
-__device__ void stockham(C2<T>* buf, int N, int nst, const int* rad, int nb, int es, int bs, const C2<T>* tw,
-                         bool inv) {
+__device__ __forceinline__ void stockham(C2<T>* buf, int N, int nst, const int* rad, int nb, int es, int bs, const C2<T>* tw,
+                         const C2<T>* gtw, bool inv) {
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = rad[s];
     switch (R) {
-      case 2: stage_reg<T, 2, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
-      case 3: stage_reg<T, 3, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
-      case 4: stage_reg<T, 4, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
-      case 5: stage_reg<T, 5, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
-      case 8: stage_reg<T, 8, EPT>(buf, N, nb, es, bs, tw, Ns, inv); break;
+#define SEG_STAGE(RR)                                                                     \
+  case RR:                                                                                \
+    if constexpr (RR <= 8 || is_odd_prime_radix<T>(RR))                                   \
+      stage_reg<T, RR, EPT>(buf, N, nb, es, bs, tw, gtw, Ns, inv);                        \
+    else                                                                                  \
+      stage_generic<T, EPT>(buf, N, RR, nb, es, bs, tw, Ns, inv);                         \
+    break;
+      SEG_STAGE(2)
+      SEG_STAGE(3)
+      SEG_STAGE(4)
+      SEG_STAGE(5)
+      SEG_STAGE(7)
+      SEG_STAGE(8)
+      SEG_STAGE(11)
+      SEG_STAGE(13)
+#undef SEG_STAGE
       default: stage_generic<T, EPT>(buf, N, R, nb, es, bs, tw, Ns, inv); break;
     }
     Ns *= R;
@@ -254,10 +314,10 @@ __device__ void stockham(C2<T>* buf, int N, int nst, const int* rad, int nb, int
 // nb * M elements of LDS scratch.  The workgroup must hold at least
 // nb * max(N, M) / EPT threads.
 template <typename T, int EPT>
-__device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw,
+__device__ __forceinline__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw,
                         const FftTab<T>& tab, C2<T>* scr, bool inv) {
   if (!p.blu) {
-    stockham<T, EPT>(buf, p.N, p.nst, p.rad, nb, es, bs, tw, inv);
+    stockham<T, EPT>(buf, p.N, p.nst, p.rad, nb, es, bs, tw, tab.tw, inv);
     return;
   }
   const int N = p.N, M = p.M;
@@ -272,7 +332,7 @@ __device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs,
     scr[idx] = v;
   }
   __syncthreads();
-  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, false);
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, tab.twM, false);
   for (int idx = threadIdx.x; idx < nb * M; idx += blockDim.x) {
     const int m = idx & (M - 1);
     C2<T> w;
@@ -285,7 +345,7 @@ __device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs,
     scr[idx] = cmul(scr[idx], w);
   }
   __syncthreads();
-  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, true);
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, tab.twM, true);
   const T invM = T(1) / T(M);
   for (int idx = threadIdx.x; idx < nb * N; idx += blockDim.x) {
     const int b = idx / N, k = idx - b * N;
@@ -299,7 +359,7 @@ __device__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs,
 // Kernel DFT of the Bluestein convolution: bf = DFT_M(d), d_m = exp(+i pi m^2 / N)
 // for m < N and at M - m, zero elsewhere (one workgroup, M elements in LDS).
 template <typename T>
-__global__ void __launch_bounds__(1024) bluestein_table_kernel(FftPlanDev p, FftTab<T> tab, C2<T>* bf_out) {
+__global__ void __launch_bounds__(kFftMaxThreads) bluestein_table_kernel(FftPlanDev p, FftTab<T> tab, C2<T>* bf_out) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const int N = p.N, M = p.M;
@@ -313,7 +373,7 @@ __global__ void __launch_bounds__(1024) bluestein_table_kernel(FftPlanDev p, Fft
     buf[m] = v;
   }
   __syncthreads();
-  stockham<T, kFftEptMax>(buf, M, p.mnst, p.mrad, 1, 1, M, tab.twM, false);
+  stockham<T, kFftEptMax>(buf, M, p.mnst, p.mrad, 1, 1, M, tab.twM, tab.twM, false);
   for (int m = threadIdx.x; m < M; m += blockDim.x) bf_out[m] = buf[m];
 }
 
@@ -327,7 +387,7 @@ hipError_t launch_bluestein_table_t(const FftPlanDev& p, const FftTab<T>& tab, C
     if (e != hipSuccess) return e;
     lds_set = true;
   }
-  const int threads = p.M / kFftEptMax < 64 ? 64 : (p.M / kFftEptMax > 1024 ? 1024 : p.M / kFftEptMax);
+  const int threads = p.M / kFftEptMax < 64 ? 64 : (p.M / kFftEptMax > kFftMaxThreads ? kFftMaxThreads : p.M / kFftEptMax);
   hipLaunchKernelGGL(fn, dim3(1), dim3(threads), (size_t)p.M * sizeof(C2<T>), st, p, tab, bf_out);
   return hipGetLastError();
 }
@@ -339,7 +399,7 @@ hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(kFftMaxThreads) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -382,7 +442,7 @@ __global__ void __launch_bounds__(1024) fft_rows_fwd_kernel(const RowFwdArgs<T>*
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(kFftMaxThreads) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const ColArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -402,6 +462,7 @@ __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T>* __rest
     buf[idx] = sp[(size_t)y * W + j];
   }
   __syncthreads();
+  // forward column DFT, division by the symbol, inverse column DFT
   fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, a.tab, tw, false);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
@@ -417,7 +478,7 @@ __global__ void __launch_bounds__(1024) fft_cols_kernel(const ColArgs<T>* __rest
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(kFftMaxThreads) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowInvArgs<T>& a = descs[find_desc(descs, ndesc)];

@@ -27,6 +27,7 @@ constexpr int kMaxL = (2 * kMaxM + 1) * (2 * kMaxM + 1);
 constexpr int kMaxK = 64;
 constexpr int kMaxSide = 4096;
 constexpr int kFftEptMax = 16;     // most complex elements per thread in one LDS FFT workgroup
+constexpr int kFftMaxThreads = 1024;  // FFT workgroup size limit
 constexpr int kMaxRadices = 24;
 constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
 
