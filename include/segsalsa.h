@@ -213,13 +213,49 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
                                           hipStream_t stream);
 
 /*
+ * Differentiable solve: gradients of a loss of the final z with respect to
+ * the input, lambda and the patch multipliers c_j, by the reverse sweep of
+ * the unrolled rounds of eqs. (12)-(14) (the method's iteration is
+ * differentiated as run; the paper itself does not train through it).
+ *
+ * segsalsa_str_solve_ckpt runs prob->iters rounds like segsalsa_str_solve
+ * (same z_out) and keeps, in `workspace`, the state (z, d1..d4) at rounds 0,
+ * S, 2S, ... with S = checkpoint_every (clamped to [1, iters]) and the final
+ * z.  segsalsa_str_backward then, given dL/dz_out, recomputes each segment of
+ * S rounds from its checkpoint and runs the reverse rounds, and writes
+ *   grad_input    [K][H][W]  dL/d input (probabilities or logits, as given);
+ *   grad_lambda   DEVICE, 1 double, dL/d lambda (may be NULL);
+ *   grad_weights  DEVICE, L doubles, dL/d c_j (may be NULL).
+ * The two calls must get the same problem, precision, checkpoint_every,
+ * input and workspace, with the workspace untouched in between.  Memory:
+ * about (ceil(iters / S) + S) states of (3 + 2L) K H W elements each.
+ * The gradient is the derivative of the closed forms that the forward
+ * rounds evaluate, taken on the side each branch of the proximity
+ * operators computes (max(v, 0) has slope 1 for v > 0 only; the Schatten
+ * shrink is differentiated through its eigenvalues, with the divided
+ * difference at merged singular values).
+ * Restrictions (SEGSALSA_ERR_UNSUPPORTED): residual_every, tol, warm_start
+ * and use_graph must be 0.
+ */
+segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
+                                                 int32_t checkpoint_every, size_t *bytes /* HOST, out */);
+segsalsa_status segsalsa_str_solve_ckpt(const segsalsa_problem *prob, segsalsa_precision precision,
+                                        int32_t checkpoint_every, const void *input, void *z_out, void *workspace,
+                                        size_t workspace_bytes, hipStream_t stream);
+segsalsa_status segsalsa_str_backward(const segsalsa_problem *prob, segsalsa_precision precision,
+                                      int32_t checkpoint_every, const void *input, const void *grad_z,
+                                      void *grad_input, double *grad_lambda, double *grad_weights, void *workspace,
+                                      size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Instrumentation (not part of the method): per-phase GPU time of the rounds
  * enqueued by segsalsa_str_solve, measured with HIP events recorded on the
  * caller's stream immediately before and after each kernel launch.  Off by
  * default; enabling it adds two event records per launch.
  *   phases: 0 = fused proximity/multiplier/J^T kernel, 1 = fold + row DFT,
  *           2 = column DFT / symbol division / inverse column DFT,
- *           3 = inverse row DFT, 4 = reserved.
+ *           3 = inverse row DFT, 4 = reverse-sweep proximity kernel
+ *           (segsalsa_str_backward; its solves count under 1-3).
  * segsalsa_profile_read waits for the recorded events, adds their elapsed
  * times to running per-phase totals, and copies the totals (milliseconds and
  * launch counts, SEGSALSA_NUM_PHASES entries each, HOST, either may be NULL);

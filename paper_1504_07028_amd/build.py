@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsegsalsa.so")
-SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "misc_kernels.hip", "residual_kernels.hip"]
+SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "misc_kernels.hip", "residual_kernels.hip", "adjoint_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

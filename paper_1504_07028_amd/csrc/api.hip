@@ -93,6 +93,8 @@ struct Plan {
   TileGeom g;
   int nw, kpw;   // prox workgroup: wavefronts and classes per wavefront
   size_t prox_lds;
+  int anw, akpw;  // adjoint workgroup (differentiable solves only)
+  size_t adj_lds;
   FftPlanDev frow, fcol;
   int rows_per_block, row_threads, row_ept;
   size_t row_lds;
@@ -139,7 +141,12 @@ bool choose_tiles(Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
   const size_t part = 12 * (size_t)p.nw * 64;
-  auto lds_of = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 16; };
+  auto fwd_lds = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 16; };
+  // reverse sweep: z, the solved cotangent and the accumulator over the grown tile
+  auto adj_lds = [&](const TileGeom& g) {
+    return p.anw ? (3 * (size_t)p.K * g.ER * g.EC + 20 * (size_t)p.anw * 64) * p.ts + 16 : 0;
+  };
+  auto lds_of = [&](const TileGeom& g) { return std::max(fwd_lds(g), adj_lds(g)); };
   // resident workgroups per CU allowed by the register budget of the chosen instantiation
   const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw) / 256);
   const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
@@ -149,7 +156,8 @@ bool choose_tiles(Plan& p) {
     TileGeom g = tile_geom(p, fr, fc);
     if (lds_of(g) <= kLdsBudget && fold_lists_fit(g)) {
       p.g = g;
-      p.prox_lds = lds_of(g);
+      p.prox_lds = fwd_lds(g);
+      p.adj_lds = adj_lds(g);
       return true;
     }
   }
@@ -177,7 +185,8 @@ bool choose_tiles(Plan& p) {
   }
   if (!have) return false;
   p.g = best;
-  p.prox_lds = lds_of(best);
+  p.prox_lds = fwd_lds(best);
+  p.adj_lds = adj_lds(best);
   return true;
 }
 
@@ -205,6 +214,7 @@ struct Common {
   double p;
   int iters, logits, every, warm, graph;
   double tol;
+  int grad = 0;   // plan for the reverse sweep as well (tiles sized for its LDS)
 };
 
 segsalsa_status validate_common(int M, const double* weights, double p, int iters, int logits, int every, double tol,
@@ -290,6 +300,24 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     p.nw = ceil_div(K, 4);
     if (p.nw * 64 > prox_max_threads_rt(p.fp64, p.M, 4))
       return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d do not fit one workgroup", K, p.M);
+  }
+  p.anw = p.akpw = 0;
+  p.adj_lds = 0;
+  if (c.grad) {
+    for (int kpw : {1, 2, 4}) {
+      const int nw = ceil_div(K, kpw);
+      if (nw <= 16 && nw * 64 <= adj_max_threads_rt(p.fp64, p.M, kpw)) {
+        p.akpw = kpw;
+        p.anw = nw;
+        break;
+      }
+    }
+    if (p.akpw == 0) {
+      p.akpw = 4;
+      p.anw = ceil_div(K, 4);
+      if (p.anw * 64 > adj_max_threads_rt(p.fp64, p.M, 4))
+        return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d do not fit one adjoint workgroup", K, p.M);
+    }
   }
   if (!choose_tiles(p)) return fail(SEGSALSA_ERR_UNSUPPORTED, "no tile shape fits LDS for K = %d, M = %d", K, p.M);
   const size_t cs = 2 * p.ts;
@@ -435,7 +463,9 @@ struct ImgRun {
 struct Batch {
   Common c;
   std::vector<ImgRun> im;
-  size_t off_tab[5];   // prox, prox with residuals, row DFT, column solve, inverse row DFT
+  // prox, prox with residuals, row DFT, column solve, inverse row DFT, and for
+  // the reverse sweep the row DFT of the cotangent and its inverse into rb
+  size_t off_tab[7];
   size_t total;
 };
 
@@ -446,6 +476,7 @@ size_t desc_size(int which) {
     case 1: return sizeof(ProxArgs<T>);
     case 2: return sizeof(RowFwdArgs<T>);
     case 3: return sizeof(ColArgs<T>);
+    case 5: return sizeof(RowFwdArgs<T>);
     default: return sizeof(RowInvArgs<T>);
   }
 }
@@ -465,7 +496,7 @@ segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, cons
     b.im[i].mu = mu[i];
     off = align_up(off + b.im[i].plan.total);
   }
-  for (int t = 0; t < 5; ++t) {
+  for (int t = 0; t < 7; ++t) {
     b.off_tab[t] = off;
     off = align_up(off + (size_t)n * (c.fp64 ? desc_size<double>(t) : desc_size<float>(t)));
   }
@@ -508,7 +539,8 @@ FftTab<T> col_tab(const Plan& p, void* base) {
 
 template <typename T>
 hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& active, void* const* zs,
-                         const void* const* ins, LaunchSet& ls, hipStream_t st) {
+                         const void* const* ins, LaunchSet& ls, hipStream_t st, void* const* adj_acc = nullptr,
+                         void* const* adj_r = nullptr) {
   (void)ins;
   const Common& c = b.c;
   ls = LaunchSet();
@@ -626,8 +658,40 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     if ((e = launch_store(wsp<char>(ws, b.off_tab[2]), rf.data(), rf.size() * sizeof(rf[0]), st)) != hipSuccess) return e;
     if ((e = launch_store(wsp<char>(ws, b.off_tab[3]), ca.data(), ca.size() * sizeof(ca[0]), st)) != hipSuccess) return e;
     if ((e = launch_store(wsp<char>(ws, b.off_tab[4]), ri.data(), ri.size() * sizeof(ri[0]), st)) != hipSuccess) return e;
+    if (adj_acc && adj_r) {  // reverse sweep: fold the cotangent's partial sums, solve into rb
+      for (size_t q = 0; q < active.size(); ++q) {
+        rf[q].acc = reinterpret_cast<const T*>(adj_acc[active[q]]);
+        ri[q].z = reinterpret_cast<T*>(adj_r[active[q]]);
+      }
+      if ((e = launch_store(wsp<char>(ws, b.off_tab[5]), rf.data(), rf.size() * sizeof(rf[0]), st)) != hipSuccess)
+        return e;
+      if ((e = launch_store(wsp<char>(ws, b.off_tab[6]), ri.data(), ri.size() * sizeof(ri[0]), st)) != hipSuccess)
+        return e;
+    }
   }
   return hipSuccess;
+}
+
+// The z-update solve A z = rhs (eq. (12)) by the three FFT passes, with the
+// row tables `fwd_tab` (fold + row DFT) and `inv_tab` (inverse row DFT).
+template <typename T>
+hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, int fwd_tab, int inv_tab) {
+  hipError_t e;
+  PhaseTimer t1(1, st);
+  e = launch_rows_fwd(wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
+                      ls.row_lds, st);
+  t1.stop();
+  if (e != hipSuccess) return e;
+  PhaseTimer t2(2, st);
+  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads, ls.col_lds,
+                  st);
+  t2.stop();
+  if (e != hipSuccess) return e;
+  PhaseTimer t3(3, st);
+  e = launch_rows_inv(wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
+                      ls.row_lds, st);
+  t3.stop();
+  return e;
 }
 
 template <typename T>
@@ -643,21 +707,7 @@ hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStrea
     }
     t0.stop();
   }
-  PhaseTimer t1(1, st);
-  e = launch_rows_fwd(wsp<RowFwdArgs<T>>(ws, b.off_tab[2]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_lds, st);
-  t1.stop();
-  if (e != hipSuccess) return e;
-  PhaseTimer t2(2, st);
-  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads, ls.col_lds,
-                  st);
-  t2.stop();
-  if (e != hipSuccess) return e;
-  PhaseTimer t3(3, st);
-  e = launch_rows_inv(wsp<RowInvArgs<T>>(ws, b.off_tab[4]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_lds, st);
-  t3.stop();
-  return e;
+  return enqueue_fft<T>(b, ls, ws, st, 2, 4);
 }
 
 template <typename T>
@@ -683,10 +733,11 @@ DiagArgs<T> diag_args(const Batch& b, int i, void* ws, void* z) {
   return da;
 }
 
-// Set-up and initialisation of every image, then all rounds.
+// Set-up (tables) of every image, initialisation unless `init` is false, and
+// the upload of the launch descriptors.
 template <typename T>
-hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
-                         LaunchSet& ls) {
+hipError_t enqueue_prepare(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
+                           LaunchSet& ls, bool init, void* const* adj_acc = nullptr, void* const* adj_r = nullptr) {
   hipError_t e;
   const Common& c = b.c;
   const int n = (int)b.im.size();
@@ -719,7 +770,7 @@ hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* 
       const FftTab<T> t = col_tab<T>(p, base);
       if ((e = launch_bluestein_table(p.fcol, t, wsp<C2<T>>(base, p.off_bfH), st)) != hipSuccess) return e;
     }
-    if (!c.warm) {
+    if (init) {
       if ((e = launch_fill_zero(wsp<char>(base, p.off_flags), 64, st)) != hipSuccess) return e;
       if ((e = launch_fill_zero(wsp<char>(base, p.off_d2), p.off_acc - p.off_d2, st)) != hipSuccess) return e;
       InitArgs<T> ia;
@@ -736,7 +787,16 @@ hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* 
   }
   std::vector<int> active(n);
   for (int i = 0; i < n; ++i) active[i] = i;
-  if ((e = upload_tables<T>(b, ws, active, zs, ins, ls, st)) != hipSuccess) return e;
+  return upload_tables<T>(b, ws, active, zs, ins, ls, st, adj_acc, adj_r);
+}
+
+// Set-up and initialisation of every image, then all rounds.
+template <typename T>
+hipError_t enqueue_solve(const Batch& b, void* ws, void* const* zs, const void* const* ins, hipStream_t st,
+                         LaunchSet& ls) {
+  hipError_t e;
+  const Common& c = b.c;
+  if ((e = enqueue_prepare<T>(b, ws, zs, ins, st, ls, !c.warm)) != hipSuccess) return e;
   if (c.every == 0) {
     for (int it = 0; it < c.iters; ++it)
       if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return e;
@@ -906,16 +966,16 @@ segsalsa_status run_graph(const Batch& b, void* ws, void* const* zs, const void*
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs, &graph);
   if (ee != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return hip_fail(ee, "capture");
   }
   if (e != hipSuccess) return hip_fail(e, "end capture");
   hipGraphExec_t exec = nullptr;
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_fail(e, "graph instantiate");
   if (g_graphs.size() >= kGraphCache) {
-    hipGraphExecDestroy(g_graphs.front().exec);
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
     g_graphs.erase(g_graphs.begin());
   }
   g_graphs.push_back({key, dev, exec});
@@ -974,6 +1034,186 @@ hipError_t run_state(const Plan& p, void* ws, int to_canon, const void* ph, cons
   a.d3 = const_cast<T*>(reinterpret_cast<const T*>(d3));
   a.d4 = const_cast<T*>(reinterpret_cast<const T*>(d4));
   return launch_state(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// Differentiable solve: forward rounds with checkpoints, then the reverse
+// sweep.  Workspace = the single-image solve region and its tables, then
+//   zw      [K][H][W]  z of the rounds being run
+//   r       [K][H][W]  rb = A^{-1} zb' of the reverse round
+//   bst     cotangents of the multipliers (the layout of dm, d2)
+//   pbar    tile layout, cotangent of p_hat from the data term
+//   bacc    grown-tile partial sums of the cotangent of z
+//   gpart   [tiles][L + 2] FP64 per-tile parameter totals, gtot [L + 2]
+//   ck      ceil(iters / S) checkpoints (z, multipliers) at rounds 0, S, 2S, ...
+//   zN      z after the last round
+//   seg     S - 1 slots of (z, multipliers) recomputed inside one segment
+// ---------------------------------------------------------------------------
+struct GradLayout {
+  Batch b;
+  int S = 1, nck = 1, nseg = 0;
+  size_t zbytes = 0, sbytes = 0;
+  size_t off_zw, off_r, off_bst, off_pbar, off_bacc, off_gpart, off_gtot, off_ck, off_zN, off_seg, total;
+  size_t ck(int i) const { return off_ck + (size_t)i * (zbytes + sbytes); }
+  size_t seg(int i) const { return off_seg + (size_t)i * (zbytes + sbytes); }
+};
+
+segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision prec, int every_ck, GradLayout& gl) {
+  Common c;
+  segsalsa_status s = validate_problem(pr, prec, c);
+  if (s != SEGSALSA_OK) return s;
+  if (every_ck < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "checkpoint_every = %d < 1", every_ck);
+  if (c.every > 0 || c.tol > 0.0)
+    return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve runs a fixed number of rounds (no residual_every/tol)");
+  if (c.warm) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve starts from the input (no warm_start)");
+  if (c.graph) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve launches directly (no use_graph)");
+  c.grad = 1;
+  if ((s = make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, gl.b)) != SEGSALSA_OK) return s;
+  const Plan& p = gl.b.im[0].plan;
+  gl.S = std::max(1, std::min(every_ck, std::max(1, c.iters)));
+  gl.nck = c.iters == 0 ? 1 : ceil_div(c.iters, gl.S);
+  gl.nseg = gl.S - 1;
+  gl.zbytes = align_up((size_t)p.K * p.H * p.W * p.ts);
+  gl.sbytes = p.off_acc - p.off_dm;
+  const size_t nt = (size_t)p.g.ntiles();
+  size_t off = gl.b.total;
+  gl.off_zw = off; off = align_up(off + gl.zbytes);
+  gl.off_r = off; off = align_up(off + gl.zbytes);
+  gl.off_bst = off; off = align_up(off + gl.sbytes);
+  gl.off_pbar = off; off = align_up(off + (p.off_dm - p.off_phat));
+  gl.off_bacc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts);
+  gl.off_gpart = off; off = align_up(off + nt * (size_t)(p.L + 2) * 8);
+  gl.off_gtot = off; off = align_up(off + (size_t)(p.L + 2) * 8);
+  gl.off_ck = off; off = align_up(off + (size_t)gl.nck * (gl.zbytes + gl.sbytes));
+  gl.off_zN = off; off = align_up(off + gl.zbytes);
+  gl.off_seg = off; off = align_up(off + (size_t)gl.nseg * (gl.zbytes + gl.sbytes));
+  gl.total = off;
+  return SEGSALSA_OK;
+}
+
+// (z, multipliers) of the working region <-> a slot at `slot` (z first).
+hipError_t save_state(const GradLayout& gl, void* ws, size_t slot, hipStream_t st) {
+  const Plan& p = gl.b.im[0].plan;
+  hipError_t e = launch_copy_bytes(wsp<char>(ws, slot), wsp<char>(ws, gl.off_zw), gl.zbytes, st);
+  if (e != hipSuccess) return e;
+  return launch_copy_bytes(wsp<char>(ws, slot + gl.zbytes), wsp<char>(ws, p.off_dm), gl.sbytes, st);
+}
+
+hipError_t load_state(const GradLayout& gl, void* ws, size_t slot, hipStream_t st) {
+  const Plan& p = gl.b.im[0].plan;
+  hipError_t e = launch_copy_bytes(wsp<char>(ws, gl.off_zw), wsp<char>(ws, slot), gl.zbytes, st);
+  if (e != hipSuccess) return e;
+  return launch_copy_bytes(wsp<char>(ws, p.off_dm), wsp<char>(ws, slot + gl.zbytes), gl.sbytes, st);
+}
+
+template <typename T>
+segsalsa_status forward_ckpt_t(const GradLayout& gl, void* ws, const void* input, void* z_out, hipStream_t st) {
+  const Batch& b = gl.b;
+  void* zs[1] = {wsp<char>(ws, gl.off_zw)};
+  const void* ins[1] = {input};
+  LaunchSet ls;
+  hipError_t e = enqueue_prepare<T>(b, ws, zs, ins, st, ls, true);
+  if (e != hipSuccess) return hip_fail(e, "forward set-up");
+  for (int t = 0; t < b.c.iters; ++t) {
+    if (t % gl.S == 0 && (e = save_state(gl, ws, gl.ck(t / gl.S), st)) != hipSuccess) return hip_fail(e, "checkpoint");
+    if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return hip_fail(e, "forward round");
+  }
+  if (b.c.iters == 0 && (e = save_state(gl, ws, gl.ck(0), st)) != hipSuccess) return hip_fail(e, "checkpoint");
+  if ((e = launch_copy_bytes(wsp<char>(ws, gl.off_zN), zs[0], gl.zbytes, st)) != hipSuccess)
+    return hip_fail(e, "final z");
+  if ((e = launch_copy_bytes(z_out, zs[0], (size_t)b.im[0].plan.K * b.im[0].plan.H * b.im[0].plan.W * b.c.ts, st)) !=
+      hipSuccess)
+    return hip_fail(e, "z_out");
+  return SEGSALSA_OK;
+}
+
+template <typename T>
+segsalsa_status backward_t(const GradLayout& gl, void* ws, const void* input, const void* grad_z, void* grad_input,
+                           double* grad_lambda, double* grad_weights, hipStream_t st) {
+  const Batch& b = gl.b;
+  const ImgRun& run = b.im[0];
+  const Plan& p = run.plan;
+  void* zw = wsp<char>(ws, gl.off_zw);
+  void* rb = wsp<char>(ws, gl.off_r);
+  void* bacc = wsp<char>(ws, gl.off_bacc);
+  void* zs[1] = {zw};
+  const void* ins[1] = {input};
+  void* aacc[1] = {bacc};
+  void* ar[1] = {rb};
+  LaunchSet ls;
+  hipError_t e = enqueue_prepare<T>(b, ws, zs, ins, st, ls, false, aacc, ar);
+  if (e != hipSuccess) return hip_fail(e, "backward set-up");
+  if ((e = launch_fill_zero(wsp<char>(ws, gl.off_bst), gl.off_bacc - gl.off_bst, st)) != hipSuccess)
+    return hip_fail(e, "zero");
+  if ((e = launch_fill_zero(wsp<char>(ws, gl.off_gpart), gl.off_ck - gl.off_gpart, st)) != hipSuccess)
+    return hip_fail(e, "zero");
+  AdjIOArgs<T> io;
+  std::memset(&io, 0, sizeof(io));
+  io.g = p.g;
+  io.K = p.K;
+  io.is_logits = b.c.logits;
+  io.grad_z = reinterpret_cast<const T*>(grad_z);
+  io.input = reinterpret_cast<const T*>(input);
+  io.phat = wsp<T>(ws, p.off_phat);
+  io.pbar = wsp<T>(ws, gl.off_pbar);
+  io.acc = reinterpret_cast<T*>(bacc);
+  io.frow = wsp<int>(ws, p.off_frow);
+  io.fcol = wsp<int>(ws, p.off_fcol);
+  io.grad_input = reinterpret_cast<T*>(grad_input);
+  if ((e = launch_fill_zero(bacc, gl.off_gpart - gl.off_bacc, st)) != hipSuccess) return hip_fail(e, "zero");
+  if ((e = launch_adj_load(io, st)) != hipSuccess) return hip_fail(e, "load cotangent");
+
+  AdjArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = p.g;
+  a.K = p.K;
+  a.nw = p.anw;
+  a.r = reinterpret_cast<const T*>(rb);
+  a.phat = wsp<T>(ws, p.off_phat);
+  a.bdm = wsp<T>(ws, gl.off_bst);
+  a.bd2 = wsp<T>(ws, gl.off_bst + (p.off_d2 - p.off_dm));
+  a.pbar = wsp<T>(ws, gl.off_pbar);
+  a.acc = reinterpret_cast<T*>(bacc);
+  a.gpart = wsp<double>(ws, gl.off_gpart);
+  a.mu = run.mu;
+  a.tau = run.lambda / run.mu;
+  a.pkind = b.c.pkind;
+  for (int j = 0; j < p.L; ++j) a.c[j] = (T)b.c.w[j];
+  const int N = b.c.iters;
+  for (int sg = gl.nck - 1; sg >= 0 && N > 0; --sg) {
+    const int t0 = sg * gl.S, t1 = std::min(t0 + gl.S, N);
+    if (t1 - t0 > 1) {  // recompute the segment's states from its checkpoint
+      if ((e = load_state(gl, ws, gl.ck(sg), st)) != hipSuccess) return hip_fail(e, "restore");
+      for (int t = t0 + 1; t < t1; ++t) {
+        if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return hip_fail(e, "recompute");
+        if ((e = save_state(gl, ws, gl.seg(t - t0 - 1), st)) != hipSuccess) return hip_fail(e, "segment");
+      }
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      if ((e = enqueue_fft<T>(b, ls, ws, st, 5, 6)) != hipSuccess) return hip_fail(e, "adjoint solve");
+      const size_t cur = t == t0 ? gl.ck(sg) : gl.seg(t - t0 - 1);
+      const size_t nxt = t + 1 < t1 ? gl.seg(t - t0) : (t1 == N ? gl.off_zN : gl.ck(sg + 1));
+      a.z = wsp<T>(ws, cur);
+      a.dm = wsp<T>(ws, cur + gl.zbytes);
+      a.d2 = wsp<T>(ws, cur + gl.zbytes + (p.off_d2 - p.off_dm));
+      a.zn = wsp<T>(ws, nxt);
+      PhaseTimer t4(4, st);
+      e = launch_adj_prox(a, p.g.ntiles(), p.anw * 64, p.M, p.akpw, p.adj_lds, st);
+      t4.stop();
+      if (e != hipSuccess) return hip_fail(e, "adjoint prox");
+    }
+  }
+  if ((e = launch_adj_input(io, st)) != hipSuccess) return hip_fail(e, "input cotangent");
+  AdjParamOut o;
+  std::memset(&o, 0, sizeof(o));
+  o.tot = wsp<double>(ws, gl.off_gtot);
+  o.grad_weights = grad_weights;
+  o.grad_lambda = grad_lambda;
+  o.mu = run.mu;
+  for (int j = 0; j < p.L; ++j) o.c[j] = (double)(T)b.c.w[j];
+  if ((e = launch_adj_params(wsp<double>(ws, gl.off_gpart), p.g.ntiles(), p.L, o, st)) != hipSuccess)
+    return hip_fail(e, "parameter cotangents");
+  return SEGSALSA_OK;
 }
 
 }  // namespace
@@ -1144,6 +1384,56 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem* prob, segsalsa
   hipError_t e = p.fp64 ? run_state<double>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream)
                         : run_state<float>(p, workspace, 0, p_hat, d1, d2, d3, d4, stream);
   return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "state import kernel");
+}
+
+segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem* prob, segsalsa_precision precision,
+                                                 int32_t checkpoint_every, size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(SEGSALSA_ERR_INVALID_ARG, "bytes is NULL");
+  GradLayout gl;
+  segsalsa_status s = make_grad_layout(prob, precision, checkpoint_every, gl);
+  if (s != SEGSALSA_OK) return s;
+  *bytes = gl.total;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_solve_ckpt(const segsalsa_problem* prob, segsalsa_precision precision,
+                                        int32_t checkpoint_every, const void* input, void* z_out, void* workspace,
+                                        size_t workspace_bytes, hipStream_t stream) {
+  g_last_error.clear();
+  GradLayout gl;
+  segsalsa_status s = make_grad_layout(prob, precision, checkpoint_every, gl);
+  if (s != SEGSALSA_OK) return s;
+  const size_t ts = gl.b.c.ts;
+  if (!input || !z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "input / z_out is NULL");
+  if (input == z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "z_out aliases input");
+  if (reinterpret_cast<uintptr_t>(z_out) % ts || reinterpret_cast<uintptr_t>(input) % ts)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "input/z_out not aligned to the element size");
+  if ((s = check_ws(gl.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
+  return gl.b.c.fp64 ? forward_ckpt_t<double>(gl, workspace, input, z_out, stream)
+                     : forward_ckpt_t<float>(gl, workspace, input, z_out, stream);
+}
+
+segsalsa_status segsalsa_str_backward(const segsalsa_problem* prob, segsalsa_precision precision,
+                                      int32_t checkpoint_every, const void* input, const void* grad_z,
+                                      void* grad_input, double* grad_lambda, double* grad_weights, void* workspace,
+                                      size_t workspace_bytes, hipStream_t stream) {
+  g_last_error.clear();
+  GradLayout gl;
+  segsalsa_status s = make_grad_layout(prob, precision, checkpoint_every, gl);
+  if (s != SEGSALSA_OK) return s;
+  const size_t ts = gl.b.c.ts;
+  if (!input || !grad_z || !grad_input) return fail(SEGSALSA_ERR_INVALID_ARG, "input / grad_z / grad_input is NULL");
+  if (grad_input == input || grad_input == grad_z)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "grad_input aliases input or grad_z");
+  if (reinterpret_cast<uintptr_t>(input) % ts || reinterpret_cast<uintptr_t>(grad_z) % ts ||
+      reinterpret_cast<uintptr_t>(grad_input) % ts)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "arrays not aligned to the element size");
+  if (reinterpret_cast<uintptr_t>(grad_lambda) % 8 || reinterpret_cast<uintptr_t>(grad_weights) % 8)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "grad_lambda / grad_weights not 8-byte aligned");
+  if ((s = check_ws(gl.total, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
+  return gl.b.c.fp64 ? backward_t<double>(gl, workspace, input, grad_z, grad_input, grad_lambda, grad_weights, stream)
+                     : backward_t<float>(gl, workspace, input, grad_z, grad_input, grad_lambda, grad_weights, stream);
 }
 
 segsalsa_status segsalsa_profile_enable(int32_t on) {

@@ -66,15 +66,6 @@ hipError_t launch_setup_t(const SetupArgs<T>& a, hipStream_t st) {
 hipError_t launch_setup(const SetupArgs<float>& a, hipStream_t st) { return launch_setup_t(a, st); }
 hipError_t launch_setup(const SetupArgs<double>& a, hipStream_t st) { return launch_setup_t(a, st); }
 
-// Position of pixel (r, c) in the tile layout: (tile, step, lane).
-__device__ inline void tile_pos(const TileGeom& g, int r, int c, int& tile, int& step, int& lane) {
-  const int tr = g.trow(r), tc = g.tcol(c);
-  const int f = (r - g.r0(tr)) * g.tw(tc) + (c - g.c0(tc));
-  tile = tr * g.ntc + tc;
-  step = f >> 6;
-  lane = f & 63;
-}
-
 // Initial state: p_hat = p / 1^T p (or softmax of logits), z = p_hat, d1 = d3 = d4 = 0.
 template <typename T>
 __global__ void init_kernel(const InitArgs<T> a) {

@@ -21,73 +21,9 @@
 // races and their summation order is fixed.
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
+#include "prox_math.h"
 
 namespace segsalsa {
-
-// Multiplier N of the Schatten-p proximity operator for one pixel.
-//
-// With S = Y^T Y = [[A, B], [B, C]] the structure tensor of the (LK)x2 block
-// Y, the proximal point is Y V diag(rho) V^T where sigma_+- = sqrt(eig(S)),
-// rho = shrunk(sigma) / sigma (0 where the shrunk value is 0) and V holds the
-// eigenvectors of S.  Written as N = alpha I + beta S with beta the divided
-// difference (rho_+ - rho_-) / (lambda_+ - lambda_-), expressed in closed
-// forms that stay finite and exact as the two eigenvalues merge.
-__device__ inline void schatten_multiplier(double A, double B, double C, double tau, int pkind,
-                                           double& n11, double& n12, double& n22) {
-  if (!(tau > 0.0)) {  // lambda = 0: prox is the identity
-    n11 = 1.0; n12 = 0.0; n22 = 1.0;
-    return;
-  }
-  if (pkind == kSchatten2) {  // Frobenius norm of the block: group shrink
-    const double nrm = sqrt(fmax(A + C, 0.0));
-    const double rho = nrm > tau ? 1.0 - tau / nrm : 0.0;
-    n11 = rho; n12 = 0.0; n22 = rho;
-    return;
-  }
-  const double hs = 0.5 * (A + C);
-  const double hd = 0.5 * (A - C);
-  const double R = sqrt(hd * hd + B * B);   // (lambda_+ - lambda_-) / 2
-  const double lp = hs + R;
-  const double lm = fmax(hs - R, 0.0);
-  const double sp = sqrt(lp), sm = sqrt(lm);
-  double rm, beta;
-  if (pkind == kSchatten1) {  // soft threshold of the singular values
-    if (sm > tau) {
-      rm = 1.0 - tau / sm;
-      beta = tau / (sp * sm * (sp + sm));
-    } else if (sp > tau) {
-      rm = 0.0;
-      beta = (sp - tau) / (sp * 2.0 * R);
-    } else {
-      n11 = 0.0; n12 = 0.0; n22 = 0.0;
-      return;
-    }
-  } else {  // Schatten-inf: sigma minus its projection on the l1 ball of radius tau
-    if (sp + sm <= tau) {
-      n11 = 0.0; n12 = 0.0; n22 = 0.0;
-      return;
-    }
-    if (sp - sm >= tau) {
-      rm = 1.0;
-      beta = -tau / (sp * 2.0 * R);
-    } else {
-      const double th = 0.5 * (sp + sm - tau);
-      rm = th / sm;
-      beta = -th / (sp * sm * (sp + sm));
-    }
-  }
-  const double alpha = rm - beta * lm;
-  n11 = alpha + beta * A;
-  n12 = beta * B;
-  n22 = alpha + beta * C;
-}
-
-// 1 / (mu t) with t > 0 the root of mu t^2 - mu s t - q = 0 (g1 prox, eq. (10)).
-__device__ inline double data_prox_gain(double s, double q, double mu) {
-  const double disc = sqrt(s * s + 4.0 * q / mu);
-  if (s >= 0.0) return 2.0 / (mu * (s + disc));
-  return (disc - s) / (2.0 * q);
-}
 
 template <typename T, int M, int KPW>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))

@@ -158,6 +158,12 @@ hipError_t launch_dual_res_t(const DiagArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, a.partial, kDiagBlocks, a.out, 1);
   return hipGetLastError();
 }
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes % 16 == 0)
+    return launch_copy_t(reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), bytes / 16, st);
+  return launch_copy_t(reinterpret_cast<const unsigned char*>(src), reinterpret_cast<unsigned char*>(dst), bytes, st);
+}
+
 hipError_t launch_dual_res(const DiagArgs<float>& a, hipStream_t st) { return launch_dual_res_t(a, st); }
 hipError_t launch_dual_res(const DiagArgs<double>& a, hipStream_t st) { return launch_dual_res_t(a, st); }
 

@@ -59,6 +59,15 @@ struct TileGeom {
   __host__ __device__ int ntiles() const { return ntr * ntc; }
 };
 
+// Position of pixel (r, c) in the tile layout: (tile, step, lane).
+__host__ __device__ inline void tile_pos(const TileGeom& g, int r, int c, int& tile, int& step, int& lane) {
+  const int tr = g.trow(r), tc = g.tcol(c);
+  const int f = (r - g.r0(tr)) * g.tw(tc) + (c - g.c0(tc));
+  tile = tr * g.ntc + tc;
+  step = f >> 6;
+  lane = f & 63;
+}
+
 // The right-hand side at image row (column) x is the sum of the grown-tile
 // partial sums at every grown position that maps onto x periodically.  A
 // source row r_s scatters to r_s + [-M, M+1], so only tiles holding a source

@@ -128,4 +128,91 @@ hipError_t launch_reduce(const double* partial, int count, double* out, int slot
 hipError_t launch_labels(int K, int H, int W, const float* z, int32_t* labels, hipStream_t st);
 hipError_t launch_labels(int K, int H, int W, const double* z, int32_t* labels, hipStream_t st);
 
+// Reverse sweep (adjoint_kernels.hip).  The adjoint kernel keeps, per lane,
+// KPW classes x 2L entries of the J-split block and L FP64 partial sums of
+// the multiplier cotangents; the per-lane register estimate below follows
+// the compiler's allocation for M <= 2 (about 6 (FP32) or 8 (FP64) VGPRs per
+// offset and class over a base of ~130), so that the launch bound does not
+// force spills.
+template <typename T, int M, int KPW>
+__host__ __device__ constexpr int adj_max_threads() {
+  constexpr int L = (2 * M + 1) * (2 * M + 1);
+  constexpr int vg = sizeof(T) == 4 ? 128 + KPW * (6 * L + 4) : 136 + KPW * (8 * L + 6);
+  constexpr int wps = 512 / vg;
+  constexpr int w = wps >= 4 ? 4 : (wps < 1 ? 1 : wps);
+  return w * 4 * 64;
+}
+
+inline int adj_max_threads_rt(bool fp64, int M, int kpw) {
+#define SEG_CASE(MM)                                                                                       \
+  case MM:                                                                                                 \
+    if (fp64) return kpw == 1 ? adj_max_threads<double, MM, 1>() : kpw == 2 ? adj_max_threads<double, MM, 2>() \
+                                                                          : adj_max_threads<double, MM, 4>(); \
+    return kpw == 1 ? adj_max_threads<float, MM, 1>() : kpw == 2 ? adj_max_threads<float, MM, 2>()           \
+                                                                : adj_max_threads<float, MM, 4>();
+  switch (M) {
+    SEG_CASE(0)
+    SEG_CASE(1)
+    SEG_CASE(2)
+    SEG_CASE(3)
+    SEG_CASE(4)
+    SEG_CASE(5)
+    default: return 0;
+  }
+#undef SEG_CASE
+}
+
+template <typename T>
+struct AdjArgs {
+  TileGeom g;
+  int K, nw;
+  const T* __restrict__ z;     // [K][H][W] z before the round
+  const T* __restrict__ zn;    // [K][H][W] z after the round
+  const T* __restrict__ r;     // [K][H][W] A^{-1} applied to the cotangent of zn
+  const T* __restrict__ phat;  // tile layout
+  const T* __restrict__ dm;    // multipliers before the round (tile layout)
+  const T* __restrict__ d2;
+  T* __restrict__ bdm;         // their cotangents: in, after the round; out, before it
+  T* __restrict__ bd2;
+  T* __restrict__ pbar;        // tile layout, accumulated cotangent of p_hat (data term)
+  T* __restrict__ acc;         // [tile][K][ER][EC] partial sums of the cotangent of z
+  double* __restrict__ gpart;  // [tile][L + 2] running totals: c_j, lambda * mu, <D rb, D zn>
+  double mu, tau;
+  int pkind;
+  T c[kMaxL];
+};
+
+template <typename T>
+struct AdjIOArgs {
+  TileGeom g;
+  int K, is_logits;
+  const T* grad_z;     // [K][H][W]
+  const T* input;      // [K][H][W]
+  const T* phat;       // tile layout
+  const T* pbar;       // tile layout
+  T* acc;              // grown-tile partial sums
+  const int* frow;
+  const int* fcol;
+  T* grad_input;       // [K][H][W]
+};
+
+struct AdjParamOut {
+  double* tot;           // [L + 2] device scratch
+  double* grad_weights;  // [L] device, may be null
+  double* grad_lambda;   // [1] device, may be null
+  double mu;
+  double c[kMaxL];       // multipliers as applied (rounded to the element type)
+};
+
+hipError_t launch_adj_prox(const AdjArgs<float>& a, int blocks, int threads, int M, int kpw, size_t lds,
+                           hipStream_t st);
+hipError_t launch_adj_prox(const AdjArgs<double>& a, int blocks, int threads, int M, int kpw, size_t lds,
+                           hipStream_t st);
+hipError_t launch_adj_load(const AdjIOArgs<float>& a, hipStream_t st);
+hipError_t launch_adj_load(const AdjIOArgs<double>& a, hipStream_t st);
+hipError_t launch_adj_input(const AdjIOArgs<float>& a, hipStream_t st);
+hipError_t launch_adj_input(const AdjIOArgs<double>& a, hipStream_t st);
+hipError_t launch_adj_params(const double* gpart, int ntiles, int L, const AdjParamOut& o, hipStream_t st);
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
+
 }  // namespace segsalsa

@@ -92,6 +92,14 @@ def lib():
     L.segsalsa_str_solve_batch.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params), c_int32,
                                            c_void_p, c_void_p, c_void_p, c_size_t, POINTER(segsalsa_stats), c_void_p]
     L.segsalsa_str_solve_batch.restype = c_int32
+    L.segsalsa_str_grad_workspace_size.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, POINTER(c_size_t)]
+    L.segsalsa_str_grad_workspace_size.restype = c_int32
+    L.segsalsa_str_solve_ckpt.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                          c_size_t, c_void_p]
+    L.segsalsa_str_solve_ckpt.restype = c_int32
+    L.segsalsa_str_backward.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.segsalsa_str_backward.restype = c_int32
     L.segsalsa_profile_enable.argtypes = [c_int32]
     L.segsalsa_profile_enable.restype = c_int32
     L.segsalsa_profile_read.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), c_int32]
@@ -261,7 +269,80 @@ def segsalsa_str_solve_batch(images, params: BatchParams, inp, z_out, workspace,
                  flags=x.flags) for x in st]
 
 
-PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "reserved")
+def segsalsa_str_grad_workspace_size(problem: Problem, precision: int, checkpoint_every: int) -> int:
+    n = c_size_t(0)
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_grad_workspace_size(ctypes.byref(s), int(precision), int(checkpoint_every),
+                                                  ctypes.byref(n)))
+    return int(n.value)
+
+
+def segsalsa_str_solve_ckpt(problem: Problem, checkpoint_every: int, inp, z_out, workspace, stream=None):
+    nel = problem.K * problem.H * problem.W
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_solve_ckpt(ctypes.byref(s), _prec(z_out.dtype), int(checkpoint_every),
+                                         _dev_ptr(inp, "input", z_out.dtype, nel), _dev_ptr(z_out, "z_out", None, nel),
+                                         _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(),
+                                         _stream(stream)))
+
+
+def segsalsa_str_backward(problem: Problem, checkpoint_every: int, inp, grad_z, grad_input, workspace,
+                          grad_lambda=None, grad_weights=None, stream=None):
+    """Reverse sweep after segsalsa_str_solve_ckpt: writes grad_input and, if given, the FP64 device
+    tensors grad_lambda [1] and grad_weights [L]."""
+    nel = problem.K * problem.H * problem.W
+    L = (2 * problem.patch_radius + 1) ** 2
+    dt = grad_z.dtype
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_backward(
+        ctypes.byref(s), _prec(dt), int(checkpoint_every), _dev_ptr(inp, "input", dt, nel),
+        _dev_ptr(grad_z, "grad_z", dt, nel), _dev_ptr(grad_input, "grad_input", dt, nel),
+        _dev_ptr(grad_lambda, "grad_lambda", torch.float64, 1),
+        _dev_ptr(grad_weights, "grad_weights", torch.float64, L),
+        _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
+
+
+class SegSalsaSTR(torch.autograd.Function):
+    """z = SegSALSA-STR(input; lambda, c) as an autograd function.
+
+    apply(inp, lam, weights, patch_radius, schatten_p, mu, iters, input_is_logits, checkpoint_every)
+    inp: device tensor [K][H][W]; lam: 0-d tensor or float; weights: tensor or list of L multipliers.
+    The forward keeps checkpoints in a workspace saved for the backward, which calls the reverse sweep.
+    """
+
+    @staticmethod
+    def forward(ctx, inp, lam, weights, patch_radius, schatten_p=1.0, mu=1.0, iters=100, input_is_logits=False,
+                checkpoint_every=10):
+        inp = inp.contiguous()
+        K, H, W = inp.shape
+        lam_f = float(lam)
+        w = [float(x) for x in (weights.tolist() if isinstance(weights, torch.Tensor) else weights)]
+        pr = Problem(K, H, W, patch_radius, w, schatten_p, lam_f, mu, iters, input_is_logits)
+        need = segsalsa_str_grad_workspace_size(pr, _prec(inp.dtype), checkpoint_every)
+        ws = torch.empty(need, dtype=torch.uint8, device=inp.device)
+        z = torch.empty_like(inp)
+        segsalsa_str_solve_ckpt(pr, checkpoint_every, inp, z, ws)
+        ctx.pr, ctx.ck, ctx.ws = pr, checkpoint_every, ws
+        ctx.lam_is_tensor = isinstance(lam, torch.Tensor)
+        ctx.w_is_tensor = isinstance(weights, torch.Tensor)
+        ctx.save_for_backward(inp)
+        return z
+
+    @staticmethod
+    def backward(ctx, gz):
+        (inp,) = ctx.saved_tensors
+        pr = ctx.pr
+        L = (2 * pr.patch_radius + 1) ** 2
+        gi = torch.empty_like(inp)
+        gl = torch.empty(1, dtype=torch.float64, device=inp.device)
+        gw = torch.empty(L, dtype=torch.float64, device=inp.device)
+        segsalsa_str_backward(pr, ctx.ck, inp, gz.contiguous(), gi, ctx.ws, gl, gw)
+        ctx.ws = None
+        return (gi, gl[0] if ctx.lam_is_tensor else None, gw if ctx.w_is_tensor else None,
+                None, None, None, None, None, None)
+
+
+PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "adjoint_prox")
 
 
 def segsalsa_profile_enable(on: bool):

@@ -136,3 +136,56 @@ def test_gpus_flag_rejected():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def grad_size(S, pr, ck, prec=1):
+    n = ctypes.c_size_t(0)
+    s = pr.c_struct()
+    return S.lib().segsalsa_str_grad_workspace_size(ctypes.byref(s), prec, ck, ctypes.byref(n)), n.value
+
+
+def test_grad_workspace_size_and_restrictions(S):
+    st, base = grad_size(S, base_problem(S, iters=20), 10)
+    assert st == OK and base > status_of_size(S, base_problem(S, iters=20), 1)[1]
+    # states kept: ceil(20 / S) checkpoints + S - 1 segment slots: 20 (S = 1), 11 (S = 10), 8 (S = 5)
+    assert grad_size(S, base_problem(S, iters=20), 1)[1] > base
+    assert grad_size(S, base_problem(S, iters=20), 5)[1] < base
+    assert grad_size(S, base_problem(S, iters=0), 10)[0] == OK
+    assert grad_size(S, base_problem(S), 0)[0] == INVALID
+    assert grad_size(S, base_problem(S, residual_every=2), 5)[0] == UNSUPPORTED
+    assert grad_size(S, base_problem(S, residual_every=2, tol=1e-3), 5)[0] == UNSUPPORTED
+    assert grad_size(S, base_problem(S, warm_start=True), 5)[0] == UNSUPPORTED
+    assert grad_size(S, base_problem(S, use_graph=True), 5)[0] == UNSUPPORTED
+    assert grad_size(S, base_problem(S, K=1), 5)[0] == INVALID
+
+
+def test_grad_argument_errors_before_launch(S):
+    """Host-side checks of the differentiable entry points; fake addresses are never dereferenced."""
+    L = S.lib()
+    pr = base_problem(S)
+    st, need = grad_size(S, pr, 2)
+    assert st == OK
+    s = pr.c_struct()
+    V = ctypes.c_void_p
+    fin, fz, fg, fgi, fws = 0x100000, 0x200000, 0x300000, 0x400000, 0x500000
+
+    def ckpt(inp, z, ws, nbytes):
+        return L.segsalsa_str_solve_ckpt(ctypes.byref(s), 1, 2, V(inp), V(z), V(ws), nbytes, None)
+
+    def bwd(inp, gz, gi, gl, gw, ws, nbytes, ck=2):
+        return L.segsalsa_str_backward(ctypes.byref(s), 1, ck, V(inp), V(gz), V(gi), V(gl), V(gw), V(ws), nbytes,
+                                       None)
+
+    assert ckpt(None, fz, fws, need) == INVALID
+    assert ckpt(fin, None, fws, need) == INVALID
+    assert ckpt(fin, fin, fws, need) == INVALID
+    assert ckpt(fin + 4, fz, fws, need) == INVALID
+    assert ckpt(fin, fz, fws, need - 1) == WORKSPACE
+    assert ckpt(fin, fz, None, need) == WORKSPACE
+    assert bwd(None, fg, fgi, None, None, fws, need) == INVALID
+    assert bwd(fin, None, fgi, None, None, fws, need) == INVALID
+    assert bwd(fin, fg, None, None, None, fws, need) == INVALID
+    assert bwd(fin, fg, fg, None, None, fws, need) == INVALID          # grad_input aliases grad_z
+    assert bwd(fin, fg, fgi, 0x600004, None, fws, need) == INVALID     # misaligned grad_lambda
+    assert bwd(fin, fg, fgi, None, None, fws, need - 1) == WORKSPACE
+    assert bwd(fin, fg, fgi, None, None, fws, need, ck=0) == INVALID
