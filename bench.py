@@ -28,8 +28,9 @@ UNIT = "pixel·class·iterations/s"
 HBM_PEAK_GBS = 8000.0
 Z_TOL = 2e-4
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_1504_07028_amd/csrc/prox_kernel.hip", "paper_1504_07028_amd/csrc/segsalsa_internal.h",
-                  "paper_1504_07028_amd/csrc/segsalsa_kernels.h", "paper_1504_07028_amd/csrc/api.hip"]
+KERNEL_SOURCES = ["paper_1504_07028_amd/csrc/prox_kernel.hip", "paper_1504_07028_amd/csrc/prox_math.h",
+                  "paper_1504_07028_amd/csrc/segsalsa_internal.h", "paper_1504_07028_amd/csrc/segsalsa_kernels.h",
+                  "paper_1504_07028_amd/csrc/api.hip"]
 
 
 def log(msg):
@@ -112,6 +113,60 @@ def cpu_baseline(wl, probs, weights, budget_s: float):
                        f"1 thread (BLAS/FFT limited to 1), {dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
 
 
+def bench_adjoint(S, torch, synth, steps, warmup, ck=10):
+    """Differentiable solve on the 256x256, K = 8, 3x3-patch, 50-round workload: one step is the
+    checkpointed forward plus the reverse sweep (gradients w.r.t. logits, lambda, patch weights)
+    of the cross-entropy of z against the label map."""
+    wl = synth.WORKLOADS["diff_256x256_k8"]
+    d = synth.make_workload(wl)
+    units = wl.n * wl.K * wl.iters
+    lab = torch.from_numpy(d["labels"]).long().cuda()
+    out = {"workload": wl.name, "checkpoint_every": ck, "unit": "pixel·class·iterations/s (forward + backward)"}
+    for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        x = torch.from_numpy(d["logits"]).to(device="cuda", dtype=dtype)
+        pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters,
+                       input_is_logits=True)
+        ws = torch.empty(S.segsalsa_str_grad_workspace_size(pr, S._prec(dtype), ck), dtype=torch.uint8,
+                         device="cuda")
+        z = torch.empty_like(x)
+        S.segsalsa_str_solve_ckpt(pr, ck, x, z, ws)
+        zd = z.double().requires_grad_(True)
+        loss = -torch.log(torch.gather(zd, 0, lab[None])[0].clamp_min(1e-6)).mean()
+        (gz,) = torch.autograd.grad(loss, zd)
+        gz = gz.to(dtype).contiguous()
+        gi = torch.empty_like(x)
+        gl = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gw = torch.zeros(wl.L, dtype=torch.float64, device="cuda")
+
+        def step():
+            S.segsalsa_str_solve_ckpt(pr, ck, x, z, ws)
+            S.segsalsa_str_backward(pr, ck, x, gz, gi, ws, gl, gw)
+
+        ms, _ = time_calls(torch, step, steps, warmup)
+        ms_fwd, _ = time_calls(torch, lambda: S.segsalsa_str_solve_ckpt(pr, ck, x, z, ws), steps, 1)
+        S.segsalsa_profile_read(reset=True)
+        S.segsalsa_profile_enable(True)
+        S.segsalsa_str_backward(pr, ck, x, gz, gi, ws, gl, gw)
+        torch.cuda.synchronize()
+        S.segsalsa_profile_enable(False)
+        tot = S.segsalsa_profile_read(reset=True)
+        adj = tot["adjoint_prox"]
+        out[tag] = {"ms_per_step": ms, "ms_forward_ckpt": ms_fwd, "ms_backward": ms - ms_fwd,
+                    "value": units / (ms * 1e-3), "backward_over_forward": (ms - ms_fwd) / ms_fwd,
+                    "adjoint_prox_avg_us": 1e3 * adj[0] / max(1, adj[1])}
+        out[tag + "_grad"] = {"lambda": float(gl.item()), "weights_l2": float(torch.linalg.vector_norm(gw).item()),
+                              "input_l2": float(torch.linalg.vector_norm(gi.double()).item())}
+        log(f"[bench] adjoint {tag}: {out[tag]}")
+        del ws, x, z, gi
+        torch.cuda.empty_cache()
+    g32, g64 = out["f32_grad"], out["f64_grad"]
+    out["grad_rel_err_fp32_vs_fp64"] = {
+        "lambda": abs(g32["lambda"] - g64["lambda"]) / abs(g64["lambda"]),
+        "weights_l2": abs(g32["weights_l2"] - g64["weights_l2"]) / g64["weights_l2"],
+        "input_l2": abs(g32["input_l2"] - g64["input_l2"]) / g64["input_l2"]}
+    return out
+
+
 def bench_batch(S, torch, synth, args):
     """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one graph launch per step."""
     B = synth.BATCH
@@ -171,6 +226,9 @@ def main():
     ap.add_argument("--schatten-p", type=float, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the differentiable solve (forward with checkpoints + reverse sweep)")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of one graph")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -198,6 +256,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written")
         del src, dst
+
+    if args.adjoint_only:
+        print(json.dumps(bench_adjoint(S, torch, synth, args.steps, args.warmup)), flush=True)
+        return
 
     if args.workload == synth.BATCH["name"]:
         print(json.dumps(bench_batch(S, torch, synth, args)), flush=True)
@@ -264,6 +326,8 @@ def main():
         out["fp64"] = {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
                        "phases_us": {k: round(v["avg_us"], 3) for k, v in res["f64"]["phases"].items()}}
         out["speedup_fp32_vs_fp64"] = res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"]
+    if not args.no_adjoint and not args.fp32_only:
+        out["adjoint"] = bench_adjoint(S, torch, synth, max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, d["probs"], d["weights"], args.cpu_seconds)
