@@ -36,7 +36,8 @@
  *    by the j-th patch offset (dy, dx) in row-major order (dy outer) and
  *    scales by the caller's multiplier c_j;
  *  - g4 is the indicator of {1_K^T xi = 1} (eq. (10)): its proximity
- *    operator is the affine projection; positivity comes from g3.
+ *    operator is the affine projection; positivity comes from g3
+ *    (g4_simplex = 1 selects the simplex projection of Sec. 4's wording).
  */
 #ifndef SEGSALSA_H
 #define SEGSALSA_H
@@ -92,6 +93,10 @@ typedef struct {
                                   the same problem, buffers and workspace (one graph launch per
                                   call; cannot be combined with residual_every).  0: launch the
                                   kernels directly                                               */
+  int32_t g4_simplex;          /* reading of the fourth split g4 (eq. (10) vs Sec. 4's wording):
+                                  0: projection onto {1_K^T xi = 1} (the definition); 1: projection
+                                  onto the probability simplex (Sec. 4's text).  Both reach the
+                                  same minimiser with g3; their iterates differ                   */
 } segsalsa_problem;
 
 /* Results reported to a HOST stats pointer. */
@@ -160,6 +165,7 @@ typedef struct {
   double tol;
   int32_t warm_start;
   int32_t use_graph;
+  int32_t g4_simplex;
 } segsalsa_batch_params;
 
 /* Workspace bytes of segsalsa_str_solve_batch for these images (HOST arrays). */
@@ -234,8 +240,8 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
  * operators computes (max(v, 0) has slope 1 for v > 0 only; the Schatten
  * shrink is differentiated through its eigenvalues, with the divided
  * difference at merged singular values).
- * Restrictions (SEGSALSA_ERR_UNSUPPORTED): residual_every, tol, warm_start
- * and use_graph must be 0.
+ * Restrictions (SEGSALSA_ERR_UNSUPPORTED): residual_every, tol, warm_start,
+ * use_graph and g4_simplex must be 0.
  */
 segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
                                                  int32_t checkpoint_every, size_t *bytes /* HOST, out */);

@@ -290,13 +290,19 @@ def prox_sum_to_one(v: np.ndarray) -> np.ndarray:
 
 @dataclass
 class Problem:
-    """Parameters of eq. (7) and of SALSA: multipliers c_j (L values), radius M, p, lambda, mu."""
+    """Parameters of eq. (7) and of SALSA: multipliers c_j (L values), radius M, p, lambda, mu.
+
+    g4 selects the reading of the fourth split (eq. (10) vs the text of Sec. 4):
+    "affine" = projection onto {1^T xi = 1} (the definition), "simplex" = projection
+    onto the probability simplex (the text's wording).
+    """
 
     c: np.ndarray
     M: int
     p: float
     lam: float
     mu: float
+    g4: str = "affine"
 
 
 @dataclass
@@ -351,7 +357,7 @@ def salsa_round(st: State, phat: np.ndarray, pr: Problem, solve_method: str = "f
     u3 = prox_positive(v3)
     d3 = u3 - v3
     v4 = z - st.d4
-    u4 = prox_sum_to_one(v4)
+    u4 = prox_sum_to_one(v4) if pr.g4 == "affine" else project_simplex(v4)
     d4 = u4 - v4
     rhs = (u1 + d1) + jacobian_adj(u2 + d2, pr.c, pr.M) + (u3 + d3) + (u4 + d4)
     znew = solve_gtg(rhs, pr.c, pr.M, method=solve_method)

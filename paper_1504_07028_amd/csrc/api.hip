@@ -94,6 +94,7 @@ struct Plan {
   int nw, kpw;   // prox workgroup: wavefronts and classes per wavefront
   size_t prox_lds;
   int anw, akpw;  // adjoint workgroup (differentiable solves only)
+  int g4s;        // simplex g4: the prox kernel stages v4 of all classes in LDS
   size_t adj_lds;
   FftPlanDev frow, fcol;
   int rows_per_block, row_threads, row_ept;
@@ -140,7 +141,7 @@ bool fold_lists_fit(const TileGeom& g) {
 bool choose_tiles(Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
-  const size_t part = 12 * (size_t)p.nw * 64;
+  const size_t part = 12 * (size_t)p.nw * 64 + (p.g4s ? 2 * (size_t)p.K * 64 : 0);
   auto fwd_lds = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 16; };
   // reverse sweep: z, the solved cotangent and the accumulator over the grown tile
   auto adj_lds = [&](const TileGeom& g) {
@@ -214,11 +215,12 @@ struct Common {
   double p;
   int iters, logits, every, warm, graph;
   double tol;
+  int g4s = 0;    // g4 as the probability-simplex projection
   int grad = 0;   // plan for the reverse sweep as well (tiles sized for its LDS)
 };
 
 segsalsa_status validate_common(int M, const double* weights, double p, int iters, int logits, int every, double tol,
-                                int warm, int graph, segsalsa_precision prec, Common& c) {
+                                int warm, int graph, int g4s, segsalsa_precision prec, Common& c) {
   if (prec != SEGSALSA_FP32 && prec != SEGSALSA_FP64) return fail(SEGSALSA_ERR_INVALID_ARG, "bad precision %d", (int)prec);
   if (M < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_radius = %d < 0", M);
   if (M > kMaxM) return fail(SEGSALSA_ERR_UNSUPPORTED, "patch_radius = %d > %d", M, kMaxM);
@@ -237,6 +239,7 @@ segsalsa_status validate_common(int M, const double* weights, double p, int iter
   if (warm != 0 && warm != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "warm_start = %d", warm);
   if (graph != 0 && graph != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "use_graph = %d", graph);
   if (graph && every > 0) return fail(SEGSALSA_ERR_INVALID_ARG, "use_graph cannot be combined with residual_every");
+  if (g4s != 0 && g4s != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "g4_simplex = %d", g4s);
   c.fp64 = prec == SEGSALSA_FP64;
   c.ts = c.fp64 ? 8 : 4;
   c.M = M;
@@ -250,6 +253,7 @@ segsalsa_status validate_common(int M, const double* weights, double p, int iter
   c.tol = tol;
   c.warm = warm;
   c.graph = graph;
+  c.g4s = g4s;
   return SEGSALSA_OK;
 }
 
@@ -269,7 +273,7 @@ segsalsa_status validate_problem(const segsalsa_problem* pr, segsalsa_precision 
   segsalsa_status s = validate_image(pr->K, pr->H, pr->W, pr->lambda, pr->mu);
   if (s != SEGSALSA_OK) return s;
   return validate_common(pr->patch_radius, pr->patch_weights, pr->schatten_p, pr->iters, pr->input_is_logits,
-                         pr->residual_every, pr->tol, pr->warm_start, pr->use_graph, prec, c);
+                         pr->residual_every, pr->tol, pr->warm_start, pr->use_graph, pr->g4_simplex, prec, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -282,6 +286,7 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   p.K = K; p.H = H; p.W = W; p.M = c.M;
   p.L = c.L;
   p.P = (K + 1) / 2;
+  p.g4s = c.g4s;
   // prox workgroup: fewest classes per wavefront whose register budget allows ceil(K/kpw) wavefronts
   p.kpw = 0;
   int kpw_first = 1;
@@ -575,6 +580,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     a.mu = r.mu;
     a.tau = r.lambda / r.mu;
     a.pkind = c.pkind;
+    a.g4s = c.g4s;
     for (int j = 0; j < c.L; ++j) a.c[j] = (T)c.w[j];
     g.count += 1;
     g.blocks += p.g.ntiles();
@@ -1067,6 +1073,7 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
     return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve runs a fixed number of rounds (no residual_every/tol)");
   if (c.warm) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve starts from the input (no warm_start)");
   if (c.graph) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve launches directly (no use_graph)");
+  if (c.g4s) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve uses the affine g4 (no g4_simplex)");
   c.grad = 1;
   if ((s = make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, gl.b)) != SEGSALSA_OK) return s;
   const Plan& p = gl.b.im[0].plan;
@@ -1273,7 +1280,7 @@ static segsalsa_status batch_common(int32_t n, const segsalsa_image* imgs, const
   Common c;
   segsalsa_status s = validate_common(bp->patch_radius, bp->patch_weights, bp->schatten_p, bp->iters,
                                       bp->input_is_logits, bp->residual_every, bp->tol, bp->warm_start, bp->use_graph,
-                                      precision, c);
+                                      bp->g4_simplex, precision, c);
   if (s != SEGSALSA_OK) return s;
   std::vector<int> K(n), H(n), W(n);
   std::vector<double> lam(n), mu(n);

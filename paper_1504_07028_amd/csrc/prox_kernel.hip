@@ -8,7 +8,9 @@
 //   g2 (Schatten prior):        u2 = prox_{(lambda/mu)||.||_{S_p}}(J z - d2),
 //                               reduced to the 2x2 structure tensor (eq. (5))
 //   g3 (positivity):            u3 = max(z - d3, 0)
-//   g4 (sum to one):            u4 = (z - d4) - (1^T (z - d4) - 1) / K
+//   g4 (sum to one):            u4 = (z - d4) - (1^T (z - d4) - 1) / K, or, with
+//                               g4s, the projection of z - d4 onto the probability
+//                               simplex: u4 = max(v4 - theta, 0) with 1^T u4 = 1
 // the multiplier update d_j <- u_j - (H_j z - d_j) (eq. (14)), and scatters
 // u_j + d_j through H_j^T into a per-tile accumulator: the right-hand side
 // G^T (u + d) of the normal equations of the z-update (eq. (12)).
@@ -46,8 +48,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
   T* acc = zt + K * plane;             // [K][ER][EC] G^T(u + d) partial sums
-  // [2][6][nw][64] per-class partial sums, 16-byte aligned (also read as doubles)
+  // [2][6][nw][64] per-class partial sums, 16-byte aligned (also read as doubles);
+  // with g4s, then [2][K][64] v4 of every class (double-buffered by step like the sums)
   T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
+  T* v4buf = part + 2 * 6 * nw * 64;
 
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
@@ -92,6 +96,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         ps += pk[kk] * v1[kk];
         pq += pk[kk] * pk[kk];
         psv += v4[kk];
+        if (a.g4s) v4buf[((s & 1) * K + k) * 64 + lane] = v4[kk];
         const C2<T>* d2p = reinterpret_cast<const C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
 #pragma unroll
         for (int j = 0; j < L; ++j) {
@@ -128,7 +133,30 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       C += (double)pbuf[(5 * nw + w) * 64 + lane];
     }
     const double gain = data_prox_gain(S, Q, a.mu);
-    const T d4n = T(-(SV - 1.0) / (double)K);
+    const T d4a = T(-(SV - 1.0) / (double)K);
+    // simplex g4: threshold theta with sum_k max(v4_k - theta, 0) = 1, by
+    // Michelot's active-set iteration (theta rises, the active set shrinks,
+    // at most K passes over the pixel's K values)
+    double theta = 0.0;
+    if (a.g4s) {
+      const T* vb = v4buf + (size_t)(s & 1) * K * 64 + lane;
+      theta = (SV - 1.0) / (double)K;
+      int cnt = K;
+      for (int it = 0; it < K; ++it) {
+        double sum = 0.0;
+        int c2 = 0;
+        for (int k = 0; k < K; ++k) {
+          const double v = (double)vb[k * 64];
+          if (v > theta) {
+            sum += v;
+            ++c2;
+          }
+        }
+        if (c2 == cnt || c2 == 0) break;
+        cnt = c2;
+        theta = (sum - 1.0) / (double)c2;
+      }
+    }
     double n11, n12, n22;
     schatten_multiplier(A, B, C, a.tau, a.pkind, n11, n12, n22);
     const T m11 = T(n11 - 1.0), m12 = T(n12), m22 = T(n22 - 1.0);
@@ -140,6 +168,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         const size_t kb = stepbase + k;
         const T d1n = T((double)pk[kk] * gain);
         const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
+        const T d4n = a.g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
         const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
         a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
         a.dm[(kb * 3 + 1) * 64 + lane] = d3n;

@@ -132,6 +132,7 @@ struct ProxArgs {
   double* __restrict__ res_tile;  // non-null on checked rounds: per-tile sum of (d_new - d_old)^2
   double mu, tau;
   int pkind;
+  int g4s;                    // 1: g4 is the probability-simplex projection
   T c[kMaxL];
 };
 

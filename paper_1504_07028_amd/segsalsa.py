@@ -38,7 +38,7 @@ class segsalsa_problem(ctypes.Structure):
         ("patch_weights", POINTER(c_double)),
         ("schatten_p", c_double), ("lambda_", c_double), ("mu", c_double),
         ("iters", c_int32), ("input_is_logits", c_int32), ("residual_every", c_int32),
-        ("tol", c_double), ("warm_start", c_int32), ("use_graph", c_int32),
+        ("tol", c_double), ("warm_start", c_int32), ("use_graph", c_int32), ("g4_simplex", c_int32),
     ]
 
 
@@ -50,7 +50,7 @@ class segsalsa_image(ctypes.Structure):
 class segsalsa_batch_params(ctypes.Structure):
     _fields_ = [("patch_radius", c_int32), ("patch_weights", POINTER(c_double)), ("schatten_p", c_double),
                 ("iters", c_int32), ("input_is_logits", c_int32), ("residual_every", c_int32), ("tol", c_double),
-                ("warm_start", c_int32), ("use_graph", c_int32)]
+                ("warm_start", c_int32), ("use_graph", c_int32), ("g4_simplex", c_int32)]
 
 
 class segsalsa_stats(ctypes.Structure):
@@ -117,7 +117,8 @@ class Problem:
     """Parameters of one SegSALSA-STR problem (mirrors segsalsa_problem)."""
 
     def __init__(self, K, H, W, patch_radius, patch_weights, schatten_p=1.0, lam=1.0, mu=1.0, iters=100,
-                 input_is_logits=False, residual_every=0, tol=0.0, warm_start=False, use_graph=False):
+                 input_is_logits=False, residual_every=0, tol=0.0, warm_start=False, use_graph=False,
+                 g4_simplex=False):
         self.K, self.H, self.W, self.patch_radius = int(K), int(H), int(W), int(patch_radius)
         self.patch_weights = [float(x) for x in patch_weights]
         self.schatten_p = float(schatten_p)
@@ -125,12 +126,14 @@ class Problem:
         self.input_is_logits = bool(input_is_logits)
         self.residual_every, self.tol, self.warm_start = int(residual_every), float(tol), bool(warm_start)
         self.use_graph = bool(use_graph)
+        self.g4_simplex = bool(g4_simplex)
 
     def c_struct(self):
         w = (c_double * max(1, len(self.patch_weights)))(*self.patch_weights)
         s = segsalsa_problem(self.K, self.H, self.W, self.patch_radius, ctypes.cast(w, POINTER(c_double)),
                              self.schatten_p, self.lam, self.mu, self.iters, int(self.input_is_logits),
-                             self.residual_every, self.tol, int(self.warm_start), int(self.use_graph))
+                             self.residual_every, self.tol, int(self.warm_start), int(self.use_graph),
+                             int(self.g4_simplex))
         s._keep = w  # keep the weights array alive with the struct
         return s
 
@@ -220,18 +223,19 @@ class BatchParams:
     """Parameters shared by the images of a batch (mirrors segsalsa_batch_params)."""
 
     def __init__(self, patch_radius, patch_weights, schatten_p=1.0, iters=100, input_is_logits=False,
-                 residual_every=0, tol=0.0, warm_start=False, use_graph=False):
+                 residual_every=0, tol=0.0, warm_start=False, use_graph=False, g4_simplex=False):
         self.patch_radius = int(patch_radius)
         self.patch_weights = [float(x) for x in patch_weights]
         self.schatten_p, self.iters = float(schatten_p), int(iters)
         self.input_is_logits, self.residual_every, self.tol = bool(input_is_logits), int(residual_every), float(tol)
         self.warm_start, self.use_graph = bool(warm_start), bool(use_graph)
+        self.g4_simplex = bool(g4_simplex)
 
     def c_struct(self):
         w = (c_double * max(1, len(self.patch_weights)))(*self.patch_weights)
         s = segsalsa_batch_params(self.patch_radius, ctypes.cast(w, POINTER(c_double)), self.schatten_p, self.iters,
                                   int(self.input_is_logits), self.residual_every, self.tol, int(self.warm_start),
-                                  int(self.use_graph))
+                                  int(self.use_graph), int(self.g4_simplex))
         s._keep = w
         return s
 

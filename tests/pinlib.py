@@ -86,7 +86,7 @@ def shrink_sv(S, tau, pchoice):
     return S - np.maximum(S - th, 0.0)
 
 
-def literal_salsa(phat, c, M, pchoice, lam, mu, n_zupdates):
+def literal_salsa(phat, c, M, pchoice, lam, mu, n_zupdates, g4="affine"):
     """SALSA exactly as eqs. (12)-(14) print it, with u kept explicitly.
 
     z-update: least squares min ||G z - u - d|| on the dense G (eq. (12));
@@ -131,7 +131,13 @@ def literal_salsa(phat, c, M, pchoice, lam, mu, n_zupdates):
         unew[off3:off3 + Kn] = np.maximum(v[off3:off3 + Kn], 0.0)
         # g4: 1^T xi = 1 per pixel
         v4 = v[off3 + Kn:].reshape(K, n)
-        unew[off3 + Kn:] = (v4 - (v4.sum(axis=0) - 1.0) / K).reshape(-1)
+        if g4 == "affine":
+            unew[off3 + Kn:] = (v4 - (v4.sum(axis=0) - 1.0) / K).reshape(-1)
+        else:  # probability simplex, threshold by bisection per pixel
+            u4 = np.empty_like(v4)
+            for i in range(n):
+                u4[:, i] = simplex_proj_vec(v4[:, i])
+            unew[off3 + Kn:] = u4.reshape(-1)
         u = unew
         d = d - (Gz - u)
     return z.reshape(K, H, W)

@@ -189,3 +189,13 @@ def test_grad_argument_errors_before_launch(S):
     assert bwd(fin, fg, fgi, 0x600004, None, fws, need) == INVALID     # misaligned grad_lambda
     assert bwd(fin, fg, fgi, None, None, fws, need - 1) == WORKSPACE
     assert bwd(fin, fg, fgi, None, None, fws, need, ck=0) == INVALID
+
+
+def test_g4_simplex_flag(S):
+    assert status_of_size(S, base_problem(S, g4_simplex=True))[0] == OK
+    pr = base_problem(S)
+    s = pr.c_struct()
+    s.g4_simplex = 2
+    n = ctypes.c_size_t(0)
+    assert S.lib().segsalsa_str_workspace_size(ctypes.byref(s), 0, ctypes.byref(n)) == INVALID
+    assert grad_size(S, base_problem(S, g4_simplex=True), 5)[0] == UNSUPPORTED

@@ -87,3 +87,18 @@ def test_two_pixel_two_class_brute_force():
             best = min(best, res.fun)
     assert obj_admm <= best + 1e-8
     assert abs(obj_admm - best) < 1e-7 * abs(best)
+
+
+@pytest.mark.parametrize("p", [1.0, math.inf])
+def test_simplex_g4_reaches_the_same_minimiser(p):
+    """Both readings of g4 split the same feasible set (with g3), so the limits coincide."""
+    probs, _, _ = synth.make_image(5, 5, 3, 33, 1.0, 1.0)
+    ph = probs / probs.sum(0)
+    c = synth.gaussian_patch_multipliers(1, 1.0)
+    objs = []
+    for g4 in ("affine", "simplex"):
+        pr = R.Problem(c, 1, p, 0.6, 5.0, g4=g4)
+        z, _ = _converged(probs, pr, 2000)
+        assert np.max(np.abs(z.sum(0) - 1)) < 1e-8 and z.min() > -1e-8
+        objs.append(R.objective(z, ph, pr))
+    assert abs(objs[0] - objs[1]) < 1e-9 * abs(objs[0])

@@ -94,3 +94,18 @@ def test_residuals_match_definitions():
     u = d_new + (G @ z - d_old)
     assert abs(rp - np.linalg.norm(G @ z - u)) < 1e-12 * (1 + rp)
     assert abs(rd - pr.mu * np.linalg.norm(G @ (new.z.reshape(-1) - z))) < 1e-12 * (1 + rd)
+
+
+@pytest.mark.parametrize("p", [1.0, math.inf])
+def test_simplex_g4_rounds_equal_literal_salsa(p):
+    """g4 read as the probability-simplex projection (Sec. 4 text): reduced rounds == literal loop."""
+    probs, _, _ = synth.make_image(4, 5, 4, 24, 2.0, 4.0)   # peaked probabilities: v4 leaves the simplex
+    pr = R.Problem(synth.gaussian_patch_multipliers(1, 1.0), 1, p, 0.7, 1.3, g4="simplex")
+    N = 4
+    z_lit = pinlib.literal_salsa(probs / probs.sum(0), pr.c, pr.M, p, pr.lam, pr.mu, N + 1, g4="simplex")
+    z_red = R.solve(probs, pr, N, solve_method="dense", prox2="svd")
+    assert np.max(np.abs(z_lit - z_red)) < 1e-12
+    # the two readings differ once some v4 leaves the simplex
+    pr.g4 = "affine"
+    z_aff = R.solve(probs, pr, N, solve_method="dense", prox2="svd")
+    assert np.max(np.abs(z_aff - z_red)) > 1e-6
