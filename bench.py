@@ -167,6 +167,31 @@ def bench_adjoint(S, torch, synth, steps, warmup, ck=10):
     return out
 
 
+def bench_variants(S, torch, synth, steps, warmup):
+    """The 145x145 workload with the method's variants: g4 as the simplex projection, and the
+    general Schatten p (p = 3, per-pixel Newton solve); FP32 throughput and its z error vs FP64."""
+    wl = synth.WORKLOADS["pines_145x145_k16"]
+    d = synth.make_workload(wl)
+    units = wl.n * wl.K * wl.iters
+    out = {"workload": wl.name}
+    for name, kw in (("g4_simplex", dict(schatten_p=wl.schatten_p, g4_simplex=True)), ("schatten_p3", dict(schatten_p=3.0))):
+        zs, rec = {}, {}
+        for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+            x = torch.from_numpy(d["probs"]).to(device="cuda", dtype=dtype)
+            pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], kw["schatten_p"], wl.lam, wl.mu, wl.iters,
+                           g4_simplex=kw.get("g4_simplex", False))
+            ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
+            z = torch.empty_like(x)
+            ms, _ = time_calls(torch, lambda: S.segsalsa_str_solve(pr, x, z, ws), steps, warmup)
+            zs[tag] = z.double()
+            rec[tag] = {"ms_per_step": ms, "value": units / (ms * 1e-3)}
+            del ws, x
+        rec["z_err_fp32_vs_fp64"] = float(torch.max(torch.abs(zs["f32"] - zs["f64"])).item())
+        out[name] = rec
+        log(f"[bench] variant {name}: {rec}")
+    return out
+
+
 def bench_batch(S, torch, synth, args):
     """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one graph launch per step."""
     B = synth.BATCH
@@ -328,6 +353,8 @@ def main():
         out["speedup_fp32_vs_fp64"] = res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"]
     if not args.no_adjoint and not args.fp32_only:
         out["adjoint"] = bench_adjoint(S, torch, synth, max(2, args.steps // 2), 1)
+    if not args.fp32_only:
+        out["variants"] = bench_variants(S, torch, synth, max(2, args.steps // 3), 1)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, d["probs"], d["weights"], args.cpu_seconds)

@@ -72,7 +72,9 @@ typedef struct {
   int32_t patch_radius;        /* M in [0, 5]: (2M+1) x (2M+1) patch, L = (2M+1)^2 (Sec. 3)     */
   const double *patch_weights; /* HOST, L finite multipliers c_j of P_j (eq. (4)), row-major in
                                   (dy, dx) with dy outer; not all zero                            */
-  double schatten_p;           /* 1.0, 2.0 or INFINITY (Sec. 3); anything else -> UNSUPPORTED   */
+  double schatten_p;           /* p >= 1 or INFINITY (the Schatten norm of Sec. 3): 1, 2 and inf
+                                  in closed form, other p by a per-pixel Newton solve of the
+                                  shrunk singular-value pair; p < 1 or NaN -> INVALID_ARG          */
   double lambda;               /* prior weight of eq. (6), finite, >= 0                          */
   double mu;                   /* SALSA penalty of eq. (13), finite, > 0                          */
   int32_t iters;               /* rounds, >= 0                                                    */
@@ -241,7 +243,7 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
  * shrink is differentiated through its eigenvalues, with the divided
  * difference at merged singular values).
  * Restrictions (SEGSALSA_ERR_UNSUPPORTED): residual_every, tol, warm_start,
- * use_graph and g4_simplex must be 0.
+ * use_graph and g4_simplex must be 0, and schatten_p must be 1, 2 or inf.
  */
 segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
                                                  int32_t checkpoint_every, size_t *bytes /* HOST, out */);

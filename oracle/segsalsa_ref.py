@@ -46,7 +46,7 @@ __all__ = [
     "patch_offsets", "shift", "diff_h", "diff_v", "diff_h_adj", "diff_v_adj",
     "jacobian", "jacobian_adj", "gtg_apply", "gtg_symbol", "solve_gtg",
     "prox_data", "prox_schatten", "prox_schatten_svd", "schatten_shrink",
-    "project_l1_ball", "prox_positive", "prox_sum_to_one",
+    "project_l1_ball", "project_lq_ball", "prox_positive", "prox_sum_to_one",
     "State", "init_state", "salsa_round", "solve", "labels", "project_simplex",
     "objective", "schatten_norms", "Problem",
 ]
@@ -202,12 +202,51 @@ def project_l1_ball(v: np.ndarray, radius) -> np.ndarray:
     return np.where(inside[..., None], out, proj)
 
 
+def project_lq_ball(w: np.ndarray, q: float, iters: int = 100) -> np.ndarray:
+    """Euclidean projection of each row of w (>= 0) onto the unit l_q ball, 1 < q < inf.
+
+    Outside the ball the projection y satisfies the optimality conditions
+    y_i - w_i + nu q y_i^{q-1} = 0 with sum_i y_i^q = 1 for some nu > 0.  For a
+    given nu each y_i is the root of a function increasing on [0, w_i] (inner
+    bisection), and sum_i y_i(nu)^q decreases in nu (outer bisection).
+    """
+    w = np.asarray(w, dtype=np.float64)
+    inside = np.sum(w ** q, axis=-1) <= 1.0
+
+    def y_of(nu):
+        lo = np.zeros_like(w)
+        hi = w.copy()
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            up = mid + nu[..., None] * q * mid ** (q - 1.0) > w
+            hi = np.where(up, mid, hi)
+            lo = np.where(up, lo, mid)
+        return 0.5 * (lo + hi)
+
+    nlo = np.zeros(w.shape[:-1])
+    nhi = np.ones(w.shape[:-1])
+    for _ in range(200):   # grow the upper end until sum y^q <= 1
+        big = np.sum(y_of(nhi) ** q, axis=-1) > 1.0
+        if not np.any(big & ~inside):
+            break
+        nhi = np.where(big, 2.0 * nhi, nhi)
+    for _ in range(iters):
+        mid = 0.5 * (nlo + nhi)
+        big = np.sum(y_of(mid) ** q, axis=-1) > 1.0
+        nlo = np.where(big, mid, nlo)
+        nhi = np.where(big, nhi, mid)
+    y = y_of(0.5 * (nlo + nhi))
+    return np.where(inside[..., None], w, y)
+
+
 def schatten_shrink(sig: np.ndarray, tau: float, p: float) -> np.ndarray:
     """Singular values of prox_{tau ||.||_{S_p}}: prox of tau ||.||_p on the singular values.
 
     p = 1: soft threshold (Sec. 4, the paper's choice); p = 2: group shrink of
-    the vector; p = inf: sigma minus its projection on the l1 ball of radius tau
-    (Moreau decomposition; l1 is the dual norm of l_inf).
+    the vector; p = inf: sigma minus its projection on the l1 ball of radius tau;
+    other p > 1 (the general Schatten norm of Sec. 3): sigma minus tau times the
+    projection of sigma / tau on the unit l_q ball, 1/p + 1/q = 1 (Moreau
+    decomposition; l_q is the dual norm of l_p).
     """
     sig = np.asarray(sig, dtype=np.float64)
     if p == 1.0:
@@ -218,7 +257,12 @@ def schatten_shrink(sig: np.ndarray, tau: float, p: float) -> np.ndarray:
         return sig * fac
     if math.isinf(p):
         return sig - project_l1_ball(sig, tau)
-    raise ValueError("schatten p must be 1, 2 or inf")
+    if p > 1.0:
+        if tau <= 0.0:
+            return sig.copy()
+        q = p / (p - 1.0)
+        return np.maximum(sig - tau * project_lq_ball(sig / tau, q), 0.0)
+    raise ValueError("schatten p must be >= 1")
 
 
 def _blocks(Y: np.ndarray) -> np.ndarray:
@@ -407,7 +451,9 @@ def schatten_norms(z: np.ndarray, pr: Problem) -> np.ndarray:
         return S.sum(axis=-1)
     if pr.p == 2.0:
         return np.sqrt(np.sum(S * S, axis=-1))
-    return S.max(axis=-1)
+    if math.isinf(pr.p):
+        return S.max(axis=-1)
+    return np.sum(S ** pr.p, axis=-1) ** (1.0 / pr.p)
 
 
 def objective(z: np.ndarray, phat: np.ndarray, pr: Problem, project: bool = True) -> float:

@@ -229,8 +229,7 @@ segsalsa_status validate_common(int M, const double* weights, double p, int iter
   for (int j = 0; j < L; ++j)
     if (!std::isfinite(weights[j])) return fail(SEGSALSA_ERR_INVALID_ARG, "patch weight %d not finite", j);
   if (std::isnan(p)) return fail(SEGSALSA_ERR_INVALID_ARG, "schatten_p is NaN");
-  if (!(p == 1.0 || p == 2.0 || (std::isinf(p) && p > 0)))
-    return fail(SEGSALSA_ERR_UNSUPPORTED, "schatten_p = %g (supported: 1, 2, inf)", p);
+  if (!(p >= 1.0)) return fail(SEGSALSA_ERR_INVALID_ARG, "schatten_p = %g < 1 is not a norm", p);
   if (iters < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "iters = %d < 0", iters);
   if (logits != 0 && logits != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "input_is_logits = %d", logits);
   if (every < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "residual_every = %d", every);
@@ -244,7 +243,7 @@ segsalsa_status validate_common(int M, const double* weights, double p, int iter
   c.ts = c.fp64 ? 8 : 4;
   c.M = M;
   c.L = L;
-  c.pkind = p == 1.0 ? kSchatten1 : (p == 2.0 ? kSchatten2 : kSchattenInf);
+  c.pkind = p == 1.0 ? kSchatten1 : (p == 2.0 ? kSchatten2 : (std::isinf(p) ? kSchattenInf : kSchattenP));
   for (int j = 0; j < L; ++j) c.w[j] = weights[j];
   c.p = p;
   c.iters = iters;
@@ -580,6 +579,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     a.mu = r.mu;
     a.tau = r.lambda / r.mu;
     a.pkind = c.pkind;
+    a.pval = c.p;
     a.g4s = c.g4s;
     for (int j = 0; j < c.L; ++j) a.c[j] = (T)c.w[j];
     g.count += 1;
@@ -726,6 +726,7 @@ DiagArgs<T> diag_args(const Batch& b, int i, void* ws, void* z) {
   da.g = p.g;
   da.K = p.K;
   da.pkind = b.c.pkind;
+  da.pval = b.c.p;
   da.lambda = r.lambda;
   for (int j = 0; j < p.L; ++j) {
     da.cw[j] = (double)(T)b.c.w[j];
@@ -1074,6 +1075,8 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
   if (c.warm) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve starts from the input (no warm_start)");
   if (c.graph) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve launches directly (no use_graph)");
   if (c.g4s) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve uses the affine g4 (no g4_simplex)");
+  if (c.pkind == kSchattenP)
+    return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve supports schatten_p in {1, 2, inf}");
   c.grad = 1;
   if ((s = make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, gl.b)) != SEGSALSA_OK) return s;
   const Plan& p = gl.b.im[0].plan;

@@ -158,7 +158,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       }
     }
     double n11, n12, n22;
-    schatten_multiplier(A, B, C, a.tau, a.pkind, n11, n12, n22);
+    schatten_multiplier(A, B, C, a.tau, a.pkind, a.pval, n11, n12, n22);
     const T m11 = T(n11 - 1.0), m12 = T(n12), m22 = T(n22 - 1.0);
 
 #pragma unroll

@@ -15,7 +15,53 @@ namespace segsalsa {
 // eigenvectors of S.  Written as N = alpha I + beta S with beta the divided
 // difference (rho_+ - rho_-) / (lambda_+ - lambda_-), expressed in closed
 // forms that stay finite and exact as the two eigenvalues merge.
-__device__ inline void schatten_multiplier(double A, double B, double C, double tau, int pkind,
+// Prox of tau ||.||_p (1 < p < inf, p != 2) on a pair of singular values
+// s1 >= s2 >= 0, written x = (x1, x2).  It is 0 when ||s||_q <= tau (q the dual
+// exponent).  Otherwise, with t = x2 / x1 in (0, 1] and
+// g(t) = tau (1 + t^p)^{-(p-1)/p} (tau over ||(1, t)||_p^{p-1}), the optimality
+// conditions s_i = x_i + tau x_i^{p-1} / ||x||_p^{p-1} give x1 = s1 - g(t),
+// x2 = t x1 and the scalar equation
+//   F(t) = (s1 - g(t)) t + g(t) t^{p-1} - s2 = 0,   F(0+) = -s2 <= 0 <= F(1) = s1 - s2,
+// solved by Newton's method in log t (the power laws are close to linear
+// there, also for p near 1) from t = s2 / s1 (the p = 2 direction), kept
+// inside the bracket [lo, hi] on t by a geometric bisection.
+__device__ inline void lp_shrink2(double s1, double s2, double tau, double p, double& x1, double& x2) {
+  x1 = 0.0;
+  x2 = 0.0;
+  if (!(s1 > 0.0)) return;
+  const double q = p / (p - 1.0);
+  const double r = s2 / s1;
+  if (s1 * pow(1.0 + pow(r, q), 1.0 / q) <= tau) return;
+  if (!(s2 > 0.0)) {  // rank one: a scalar soft threshold
+    x1 = s1 - tau;
+    return;
+  }
+  const double e = -(p - 1.0) / p;
+  double lo = 0.0, hi = 1.0, t = r;
+  for (int it = 0; it < 100; ++it) {
+    const double tp = pow(t, p), tpm1 = pow(t, p - 1.0);
+    const double g = tau * pow(1.0 + tp, e);
+    const double F = (s1 - g) * t + g * tpm1 - s2;
+    if (F == 0.0) break;
+    if (F > 0.0) hi = t;
+    else lo = t;
+    const double dg = -(p - 1.0) * tpm1 * g / (1.0 + tp);
+    const double dFdlogt = t * (s1 - g - dg * t + dg * tpm1) + g * (p - 1.0) * tpm1;
+    const double step = F / dFdlogt;
+    if (fabs(step) <= 4e-16) {  // converged to rounding: keep the Newton point
+      t *= exp(-step);
+      break;
+    }
+    double tn = t * exp(-step);
+    if (!(tn > lo && tn < hi)) tn = lo > 0.0 ? sqrt(lo * hi) : 0.5 * hi;
+    t = tn;
+    if (hi - lo <= 4e-16 * hi) break;
+  }
+  x1 = s1 - tau * pow(1.0 + pow(t, p), e);
+  x2 = t * x1;
+}
+
+__device__ inline void schatten_multiplier(double A, double B, double C, double tau, int pkind, double pval,
                                            double& n11, double& n12, double& n22) {
   if (!(tau > 0.0)) {  // lambda = 0: prox is the identity
     n11 = 1.0; n12 = 0.0; n22 = 1.0;
@@ -33,6 +79,17 @@ __device__ inline void schatten_multiplier(double A, double B, double C, double 
   const double lp = hs + R;
   const double lm = fmax(hs - R, 0.0);
   const double sp = sqrt(lp), sm = sqrt(lm);
+  if (pkind == kSchattenP) {  // general p: multipliers from the shrunk pair, N = rm I + (rp - rm) e+ e+^T
+    double x1, x2;
+    lp_shrink2(sp, sm, tau, pval, x1, x2);
+    const double rp = sp > 0.0 ? x1 / sp : 0.0;
+    const double rmm = sm > 0.0 ? x2 / sm : 0.0;
+    const double c2 = R > 0.0 ? hd / R : 1.0, s2 = R > 0.0 ? B / R : 0.0;
+    n11 = rmm + (rp - rmm) * 0.5 * (1.0 + c2);
+    n22 = rmm + (rp - rmm) * 0.5 * (1.0 - c2);
+    n12 = (rp - rmm) * 0.5 * s2;
+    return;
+  }
   double rm, beta;
   if (pkind == kSchatten1) {  // soft threshold of the singular values
     if (sm > tau) {

@@ -120,7 +120,10 @@ __global__ void __launch_bounds__(256) objective_kernel(const DiagArgs<T> a) {
     const double hs = 0.5 * (A + C), hd = 0.5 * (A - C);
     const double R = sqrt(hd * hd + B * B);
     const double sp = sqrt(hs + R), sm = sqrt(fmax(hs - R, 0.0));
-    const double nrm = a.pkind == kSchatten1 ? sp + sm : (a.pkind == kSchatten2 ? sqrt(fmax(A + C, 0.0)) : sp);
+    const double nrm = a.pkind == kSchatten1   ? sp + sm
+                       : a.pkind == kSchatten2 ? sqrt(fmax(A + C, 0.0))
+                       : a.pkind == kSchattenP ? pow(pow(sp, a.pval) + pow(sm, a.pval), 1.0 / a.pval)
+                                               : sp;
     val = -log(dot) + a.lambda * nrm;
   }
   const double t = block_sum(val, sh);

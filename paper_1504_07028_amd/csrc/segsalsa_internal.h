@@ -102,7 +102,7 @@ __host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, 
 }
 
 // Per-pixel arithmetic parameters of one round.
-enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3 };
+enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3, kSchattenP = 4 };
 
 // Per-image kernel arguments live in device tables; a launch covers a range
 // of images and block b belongs to the last image whose block0 <= b.
@@ -132,6 +132,7 @@ struct ProxArgs {
   double* __restrict__ res_tile;  // non-null on checked rounds: per-tile sum of (d_new - d_old)^2
   double mu, tau;
   int pkind;
+  double pval;                // the Schatten p (used when pkind == kSchattenP)
   int g4s;                    // 1: g4 is the probability-simplex projection
   T c[kMaxL];
 };

@@ -109,6 +109,7 @@ struct DiagArgs {
   TileGeom g;
   int K;
   int pkind;
+  double pval;
   double lambda, wsum;
   const T* z;        // [K][H][W] current z
   T* zprev;          // [K][H][W] z before the round; scratch for the projection in the objective

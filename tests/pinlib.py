@@ -67,6 +67,17 @@ def data_prox_closed(v, p, mu):
 def shrink_sv(S, tau, pchoice):
     """Prox of tau ||.||_p on a vector of singular values (two entries)."""
     S = np.asarray(S, dtype=float)
+    if pchoice not in (1, 2) and not math.isinf(pchoice):
+        # general p: minimise 1/2 ||x - S||^2 + tau ||x||_p directly
+        from scipy import optimize
+        f = lambda x: 0.5 * np.sum((x - S) ** 2) + tau * np.sum(np.abs(x) ** pchoice) ** (1.0 / pchoice)
+        best = None
+        for x0 in (S, 0.5 * S, S * 0 + 1e-3):
+            r = optimize.minimize(f, x0, method="Nelder-Mead",
+                                  options=dict(xatol=1e-13, fatol=1e-16, maxiter=40000))
+            if best is None or r.fun < best.fun:
+                best = r
+        return np.maximum(best.x, 0.0)
     if pchoice == 1:
         return np.maximum(S - tau, 0.0)
     if pchoice == 2:

@@ -63,15 +63,16 @@ def test_workspace_size_grows_with_problem(S):
     (dict(K=1), INVALID), (dict(K=65), UNSUPPORTED), (dict(H=0), INVALID), (dict(W=-3), INVALID),
     (dict(H=1, W=1), INVALID), (dict(H=5000), UNSUPPORTED), (dict(patch_radius=-1), INVALID),
     (dict(patch_radius=6, patch_weights=[1.0] * 169), UNSUPPORTED),
-    (dict(patch_weights=[1.0] * 8 + [math.nan]), INVALID), (dict(schatten_p=1.5), UNSUPPORTED),
-    (dict(schatten_p=math.nan), INVALID), (dict(schatten_p=0.5), UNSUPPORTED), (dict(lam=-1.0), INVALID),
+    (dict(patch_weights=[1.0] * 8 + [math.nan]), INVALID), (dict(schatten_p=1.5), OK), (dict(schatten_p=7.25), OK),
+    (dict(schatten_p=math.nan), INVALID), (dict(schatten_p=0.5), INVALID), (dict(schatten_p=-math.inf), INVALID),
+    (dict(lam=-1.0), INVALID),
     (dict(lam=math.inf), INVALID), (dict(mu=0.0), INVALID), (dict(mu=-2.0), INVALID), (dict(iters=-1), INVALID),
     (dict(tol=1e-3), INVALID), (dict(tol=-1.0), INVALID), (dict(residual_every=-1), INVALID),
 ])
 def test_invalid_problems(S, kw, code):
     st, _ = status_of_size(S, base_problem(S, **kw))
     assert st == code
-    assert S.lib().segsalsa_last_error().decode() != ""
+    assert (S.lib().segsalsa_last_error().decode() != "") == (code != OK)
 
 
 def test_bad_precision_and_null_problem(S):
@@ -199,3 +200,4 @@ def test_g4_simplex_flag(S):
     n = ctypes.c_size_t(0)
     assert S.lib().segsalsa_str_workspace_size(ctypes.byref(s), 0, ctypes.byref(n)) == INVALID
     assert grad_size(S, base_problem(S, g4_simplex=True), 5)[0] == UNSUPPORTED
+    assert grad_size(S, base_problem(S, schatten_p=3.0), 5)[0] == UNSUPPORTED

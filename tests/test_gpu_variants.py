@@ -3,6 +3,8 @@
 * g4 read as the probability-simplex projection (Sec. 4's wording) instead
   of the affine projection of the definition (eq. (10)): FP64 within 1e-9,
   FP32 within 2e-4, single and batched solves, and the 145x145 workload.
+* General Schatten p (1.25, 1.5, 3, 4.7, 10): FP64 within 1e-9, FP32 within
+  2e-4, residuals and objective, the 145x145 workload.
 """
 import math
 
@@ -112,3 +114,63 @@ def test_simplex_g4_pines_145(dtype):
     srt = np.sort(zo, axis=0)
     sure = (srt[-1] - srt[-2]) > MARGIN
     assert np.array_equal(np.argmax(zg, axis=0)[sure], np.argmax(zo, axis=0)[sure])
+
+
+# general Schatten p (Sec. 3's norm for p other than 1, 2, inf): per-pixel Newton solve in the kernel,
+# Moreau decomposition with a nested-bisection l_q projection in the oracle
+GENERAL_P_CASES = [
+    (9, 7, 4, 1, 1.5, 8),
+    (33, 45, 6, 1, 3.0, 8),
+    (40, 52, 16, 2, 4.7, 5),
+    (29, 31, 3, 0, 1.25, 8),
+    (47, 53, 5, 1, 10.0, 5),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("H,W,K,M,p,iters", GENERAL_P_CASES)
+def test_general_p_small(H, W, K, M, p, iters, dtype):
+    S = need_gpu()
+    say(f"case general p={p} H={H} W={W} K={K} M={M} iters={iters} {dtype}")
+    probs, _, _ = synth.make_image(H, W, K, 900 + H, 1.0, 1.5)
+    c = synth.gaussian_patch_multipliers(M, 1.0)
+    z, _ = solve_variant(S, probs, c, M, p, 0.8, 1.3, iters, dtype)
+    zo = oracle_variant(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
+    err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+def test_general_p_residuals_and_objective():
+    S = need_gpu()
+    p = 3.0
+    probs, _, _ = synth.make_image(24, 28, 5, 93, 1.0, 1.5)
+    c = synth.gaussian_patch_multipliers(1, 1.0)
+    z, st = solve_variant(S, probs, c, 1, p, 0.7, 1.3, 9, torch.float64, residual_every=9)
+    pr = R.Problem(np.asarray(c), 1, p, 0.7, 1.3)
+    ph = R.normalize_input(probs, False)
+    sto = R.init_state(ph, 9)
+    for _ in range(8):
+        sto = R.salsa_round(sto, ph, pr)
+    sto, rp, rd = R.salsa_round(sto, ph, pr, want_residuals=True)
+    obj = R.objective(sto.z, ph, pr)
+    say(f"  primal {st['primal_res']:.6e} vs {rp:.6e}, dual {st['dual_res']:.6e} vs {rd:.6e}, "
+        f"objective {st['objective']:.10e} vs {obj:.10e}")
+    assert abs(st["primal_res"] - rp) <= 1e-9 * rp and abs(st["dual_res"] - rd) <= 1e-9 * rd
+    assert abs(st["objective"] - obj) <= 1e-9 * abs(obj)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_general_p_pines_145(dtype):
+    """145x145, K = 16, 5x5 patch, lambda = mu = 2, Schatten-3, 4 rounds (the oracle's l_q projection is slow)."""
+    S = need_gpu()
+    wl = synth.WORKLOADS["pines_145x145_k16"]
+    d = synth.make_workload(wl)
+    iters = 4
+    say(f"case {wl.name} p=3 {iters} rounds {dtype}")
+    z, _ = solve_variant(S, d["probs"], d["weights"], wl.M, 3.0, wl.lam, wl.mu, iters, dtype)
+    zo = oracle_variant(rounded_input(d["probs"], dtype), weights_as_seen(d["weights"], dtype), wl.M, 3.0, wl.lam,
+                        wl.mu, iters)
+    err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
+    say(f"  max err {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
