@@ -192,6 +192,43 @@ def bench_variants(S, torch, synth, steps, warmup):
     return out
 
 
+def bench_sweep(S, torch, synth, wl_name="pines_145x145_k16", radii=(0, 1, 2, 3, 4, 5), dtype_name="f32",
+                iters=None, steps=1):
+    """Synthetic analogue of the patch-size experiment (Sec. 5, Fig. 1): patches 1x1 ... 11x11 with
+    Gaussian bandwidth gamma = M (the distance from the patch border to its centre; 1 for 1x1),
+    argmax labels after the rounds against the Voronoi ground truth, next to argmax p."""
+    import dataclasses
+    wl = synth.WORKLOADS[wl_name]
+    if iters is not None:
+        wl = dataclasses.replace(wl, iters=iters)
+    d = synth.make_workload(wl)
+    dtype = torch.float32 if dtype_name == "f32" else torch.float64
+    truth = torch.from_numpy(d["labels"]).cuda()
+    x = torch.from_numpy(d["probs"]).to(device="cuda", dtype=dtype)
+    lab = torch.empty(wl.H, wl.W, dtype=torch.int32, device="cuda")
+    S.segsalsa_str_labels(x, lab)
+    torch.cuda.synchronize()
+    out = {"workload": wl.name, "rounds": wl.iters, "lambda": wl.lam, "mu": wl.mu, "dtype": dtype_name,
+           "accuracy_argmax_p": float((lab == truth).float().mean().item()), "patches": []}
+    for M in radii:
+        gamma = max(M, 1)
+        c = synth.gaussian_patch_multipliers(M, float(gamma))
+        pr = S.Problem(wl.K, wl.H, wl.W, M, c, wl.schatten_p, wl.lam, wl.mu, wl.iters)
+        ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
+        z = torch.empty_like(x)
+        ms, _ = time_calls(torch, lambda: S.segsalsa_str_solve(pr, x, z, ws), steps, 1)
+        S.segsalsa_str_labels(z, lab)
+        torch.cuda.synchronize()
+        acc = float((lab == truth).float().mean().item())
+        L = (2 * M + 1) ** 2
+        out["patches"].append({"patch": f"{2 * M + 1}x{2 * M + 1}", "gamma": gamma, "L": L, "accuracy": acc,
+                               "ms_per_solve": ms, "value": wl.n * wl.K * wl.iters / (ms * 1e-3)})
+        log(f"[bench] sweep {2 * M + 1}x{2 * M + 1}: accuracy {acc:.4f}, {ms:.2f} ms")
+        del ws, z
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(S, torch, synth, args):
     """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one graph launch per step."""
     B = synth.BATCH
@@ -252,6 +289,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve measurement")
+    ap.add_argument("--sweep", action="store_true",
+                    help="patch-size sweep 1x1 ... 11x11 on the workload (accuracy vs the synthetic ground truth)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the differentiable solve (forward with checkpoints + reverse sweep)")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
@@ -281,6 +320,10 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written")
         del src, dst
+
+    if args.sweep:
+        print(json.dumps(bench_sweep(S, torch, synth, args.workload, steps=args.steps)), flush=True)
+        return
 
     if args.adjoint_only:
         print(json.dumps(bench_adjoint(S, torch, synth, args.steps, args.warmup)), flush=True)

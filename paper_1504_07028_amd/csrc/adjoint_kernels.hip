@@ -148,7 +148,7 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
       const double gq = -gain * gain / disc;
       // g2: multiplier N and the cotangent of S
       double n11, n12, n22, s11, s12, s22, dtau;
-      schatten_multiplier(A, B, C, a.tau, a.pkind, 0.0, n11, n12, n22);
+      schatten_multiplier<false>(A, B, C, a.tau, a.pkind, 0.0, n11, n12, n22);
       schatten_multiplier_vjp(A, B, C, a.tau, a.pkind, tot[7], 0.5 * tot[8], tot[9], s11, s12, s22, dtau);
       if (wid == 0) lb += dtau;
       const T m11 = T(n11), m12 = T(n12), m22 = T(n22);

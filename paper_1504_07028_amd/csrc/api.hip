@@ -708,7 +708,8 @@ hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStrea
   {
     PhaseTimer t0(0, st);
     for (const auto& g : ls.groups) {
-      e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.lds, st);
+      e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.lds,
+                      b.c.pkind == kSchattenP || b.c.g4s, st);
       if (e != hipSuccess) return e;
     }
     t0.stop();

@@ -27,7 +27,9 @@
 
 namespace segsalsa {
 
-template <typename T, int M, int KPW>
+// VAR compiles in the method's variants (general Schatten p, simplex g4);
+// the plain instantiation (p in {1, 2, inf}, affine g4) stays lean.
+template <typename T, int M, int KPW, bool VAR>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
@@ -44,6 +46,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   const int K = a.K, nw = a.nw;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int H = g.H, W = g.W;
+  const bool g4s = VAR && a.g4s;
 
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
@@ -96,7 +99,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         ps += pk[kk] * v1[kk];
         pq += pk[kk] * pk[kk];
         psv += v4[kk];
-        if (a.g4s) v4buf[((s & 1) * K + k) * 64 + lane] = v4[kk];
+        if (g4s) v4buf[((s & 1) * K + k) * 64 + lane] = v4[kk];
         const C2<T>* d2p = reinterpret_cast<const C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
 #pragma unroll
         for (int j = 0; j < L; ++j) {
@@ -138,7 +141,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     // Michelot's active-set iteration (theta rises, the active set shrinks,
     // at most K passes over the pixel's K values)
     double theta = 0.0;
-    if (a.g4s) {
+    if (g4s) {
       const T* vb = v4buf + (size_t)(s & 1) * K * 64 + lane;
       theta = (SV - 1.0) / (double)K;
       int cnt = K;
@@ -158,7 +161,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       }
     }
     double n11, n12, n22;
-    schatten_multiplier(A, B, C, a.tau, a.pkind, a.pval, n11, n12, n22);
+    schatten_multiplier<VAR>(A, B, C, a.tau, a.pkind, a.pval, n11, n12, n22);
     const T m11 = T(n11 - 1.0), m12 = T(n12), m22 = T(n22 - 1.0);
 
 #pragma unroll
@@ -168,7 +171,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         const size_t kb = stepbase + k;
         const T d1n = T((double)pk[kk] * gain);
         const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
-        const T d4n = a.g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
+        const T d4n = g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
         const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
         a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
         a.dm[(kb * 3 + 1) * 64 + lane] = d3n;
@@ -269,10 +272,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   }
 }
 
-template <typename T, int M, int KPW>
+template <typename T, int M, int KPW, bool VAR>
 static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks, int threads, size_t lds,
                                 hipStream_t st) {
-  auto fn = prox_rhs_kernel<T, M, KPW>;
+  auto fn = prox_rhs_kernel<T, M, KPW, VAR>;
   static bool lds_set = false;  // idempotent, so a racing second call is harmless
   if (!lds_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -284,38 +287,40 @@ static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks,
   return hipGetLastError();
 }
 
-template <typename T, int M>
+template <typename T, int M, bool VAR>
 static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, size_t lds,
                                 hipStream_t st) {
   switch (kpw) {
-    case 1: return launch_prox_t<T, M, 1>(d, n, blocks, threads, lds, st);
-    case 2: return launch_prox_t<T, M, 2>(d, n, blocks, threads, lds, st);
-    case 4: return launch_prox_t<T, M, 4>(d, n, blocks, threads, lds, st);
+    case 1: return launch_prox_t<T, M, 1, VAR>(d, n, blocks, threads, lds, st);
+    case 2: return launch_prox_t<T, M, 2, VAR>(d, n, blocks, threads, lds, st);
+    case 4: return launch_prox_t<T, M, 4, VAR>(d, n, blocks, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename T>
-static hipError_t launch_prox_any(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                                  hipStream_t st) {
+template <typename T, bool VAR>
+static hipError_t launch_prox_v(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+                                hipStream_t st) {
   switch (M) {
-    case 0: return launch_prox_m<T, 0>(d, n, blocks, threads, kpw, lds, st);
-    case 1: return launch_prox_m<T, 1>(d, n, blocks, threads, kpw, lds, st);
-    case 2: return launch_prox_m<T, 2>(d, n, blocks, threads, kpw, lds, st);
-    case 3: return launch_prox_m<T, 3>(d, n, blocks, threads, kpw, lds, st);
-    case 4: return launch_prox_m<T, 4>(d, n, blocks, threads, kpw, lds, st);
-    case 5: return launch_prox_m<T, 5>(d, n, blocks, threads, kpw, lds, st);
+    case 0: return launch_prox_m<T, 0, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 1: return launch_prox_m<T, 1, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 2: return launch_prox_m<T, 2, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 3: return launch_prox_m<T, 3, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 4: return launch_prox_m<T, 4, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 5: return launch_prox_m<T, 5, VAR>(d, n, blocks, threads, kpw, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                       hipStream_t st) {
-  return launch_prox_any<float>(d, n, blocks, threads, M, kpw, lds, st);
+                       bool variants, hipStream_t st) {
+  return variants ? launch_prox_v<float, true>(d, n, blocks, threads, M, kpw, lds, st)
+                  : launch_prox_v<float, false>(d, n, blocks, threads, M, kpw, lds, st);
 }
 hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                       hipStream_t st) {
-  return launch_prox_any<double>(d, n, blocks, threads, M, kpw, lds, st);
+                       bool variants, hipStream_t st) {
+  return variants ? launch_prox_v<double, true>(d, n, blocks, threads, M, kpw, lds, st)
+                  : launch_prox_v<double, false>(d, n, blocks, threads, M, kpw, lds, st);
 }
 
 }  // namespace segsalsa

@@ -61,6 +61,9 @@ __device__ inline void lp_shrink2(double s1, double s2, double tau, double p, do
   x2 = t * x1;
 }
 
+// GP = false compiles out the general-p branch (its Newton loop would raise
+// the register pressure of kernels that never take it).
+template <bool GP>
 __device__ inline void schatten_multiplier(double A, double B, double C, double tau, int pkind, double pval,
                                            double& n11, double& n12, double& n22) {
   if (!(tau > 0.0)) {  // lambda = 0: prox is the identity
@@ -79,7 +82,7 @@ __device__ inline void schatten_multiplier(double A, double B, double C, double 
   const double lp = hs + R;
   const double lm = fmax(hs - R, 0.0);
   const double sp = sqrt(lp), sm = sqrt(lm);
-  if (pkind == kSchattenP) {  // general p: multipliers from the shrunk pair, N = rm I + (rp - rm) e+ e+^T
+  if (GP && pkind == kSchattenP) {  // general p: multipliers from the shrunk pair, N = rm I + (rp - rm) e+ e+^T
     double x1, x2;
     lp_shrink2(sp, sm, tau, pval, x1, x2);
     const double rp = sp > 0.0 ? x1 / sp : 0.0;

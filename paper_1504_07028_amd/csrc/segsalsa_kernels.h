@@ -37,10 +37,11 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
 }
 
 // Per-round launches over a table of per-image descriptors in device memory.
+// variants: the instantiation with the general Schatten p and the simplex g4 compiled in
 hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                       hipStream_t st);
+                       bool variants, hipStream_t st);
 hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                       hipStream_t st);
+                       bool variants, hipStream_t st);
 
 hipError_t launch_rows_fwd(const RowFwdArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
 hipError_t launch_rows_fwd(const RowFwdArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
