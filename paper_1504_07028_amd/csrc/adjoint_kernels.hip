@@ -51,6 +51,9 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
   T* rt = zt + K * plane;              // [K][ER][EC] rb = A^{-1} zb'
   T* acc = rt + K * plane;             // [K][ER][EC] partial sums of zb
   T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
+  // [NS][64] FP64 per-pixel class sums and [10][64] FP64 per-pixel coefficients
+  double* tot = reinterpret_cast<double*>(part + 2 * NS * nw * 64);
+  double* coef = tot + NS * 64;
 
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
@@ -132,29 +135,53 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
 #pragma unroll
     for (int q = 0; q < NS; ++q) pbuf[(q * nw + wid) * 64 + lane] = mine[q];
     __syncthreads();
-    if (valid) {
-      double tot[NS];
-#pragma unroll
-      for (int q = 0; q < NS; ++q) tot[q] = 0.0;
-      for (int w = 0; w < nw; ++w)
-#pragma unroll
-        for (int q = 0; q < NS; ++q) tot[q] += (double)pbuf[(q * nw + w) * 64 + lane];
-      const double S = tot[0], Q = tot[1], PU = tot[2], SU4 = tot[3];
-      const double A = tot[4], B = tot[5], C = tot[6];
+    // class sums reduced once (wave q < NS takes sum q), the per-pixel FP64
+    // closed forms evaluated once (waves 0 and 1) and shared through LDS
+#pragma unroll 1
+    for (int q = wid; q < NS; q += nw) {
+      double t = 0.0;
+#pragma unroll 1
+      for (int w = 0; w < nw; ++w) t += (double)pbuf[(q * nw + w) * 64 + lane];
+      tot[q * 64 + lane] = t;
+    }
+    __syncthreads();
+    const int wn = nw > 1 ? 1 : 0;  // the two closed forms on two wavefronts (register peak)
+    if (wid == 0 && valid) {
+      const double S = tot[0 * 64 + lane], Q = tot[1 * 64 + lane], PU = tot[2 * 64 + lane];
       // g1: gain and its partial derivatives in s = p^T v and q = ||p||^2
       const double gain = data_prox_gain(S, Q, a.mu);
       const double disc = sqrt(S * S + 4.0 * Q / a.mu);
       const double gs = -gain / disc;
       const double gq = -gain * gain / disc;
+      coef[0 * 64 + lane] = gain;
+      coef[1 * 64 + lane] = gs * PU;
+      coef[2 * 64 + lane] = 2.0 * gq * PU;
+      coef[3 * 64 + lane] = tot[3 * 64 + lane] / (double)K;
+    }
+    if (wid == wn && valid) {
+      const double A = tot[4 * 64 + lane], B = tot[5 * 64 + lane], C = tot[6 * 64 + lane];
       // g2: multiplier N and the cotangent of S
       double n11, n12, n22, s11, s12, s22, dtau;
       schatten_multiplier<false>(A, B, C, a.tau, a.pkind, 0.0, n11, n12, n22);
-      schatten_multiplier_vjp(A, B, C, a.tau, a.pkind, tot[7], 0.5 * tot[8], tot[9], s11, s12, s22, dtau);
-      if (wid == 0) lb += dtau;
-      const T m11 = T(n11), m12 = T(n12), m22 = T(n22);
-      const T t11 = T(2.0 * s11), t12 = T(2.0 * s12), t22 = T(2.0 * s22);
-      const T mean4 = T(SU4 / (double)K);
-      const T kg = T(gs * PU);
+      schatten_multiplier_vjp(A, B, C, a.tau, a.pkind, tot[7 * 64 + lane], 0.5 * tot[8 * 64 + lane],
+                              tot[9 * 64 + lane], s11, s12, s22, dtau);
+      lb += dtau;
+      coef[4 * 64 + lane] = n11;
+      coef[5 * 64 + lane] = n12;
+      coef[6 * 64 + lane] = n22;
+      coef[7 * 64 + lane] = 2.0 * s11;
+      coef[8 * 64 + lane] = 2.0 * s12;
+      coef[9 * 64 + lane] = 2.0 * s22;
+    }
+    __syncthreads();
+    if (valid) {
+      const double gain = coef[0 * 64 + lane];
+      const double pgs = coef[1 * 64 + lane];   // (p^T ub1) g_s
+      const double pgq2 = coef[2 * 64 + lane];  // 2 (p^T ub1) g_q
+      const T mean4 = T(coef[3 * 64 + lane]);
+      const T m11 = T(coef[4 * 64 + lane]), m12 = T(coef[5 * 64 + lane]), m22 = T(coef[6 * 64 + lane]);
+      const T t11 = T(coef[7 * 64 + lane]), t12 = T(coef[8 * 64 + lane]), t22 = T(coef[9 * 64 + lane]);
+      const T kg = T(pgs);
       const int gr = r0 + lr, gc = c0 + lc;
       const size_t ic = (size_t)gr * W + gc;
       const size_t irr = (size_t)gr * W + (gc + 1 == W ? 0 : gc + 1);
@@ -170,7 +197,7 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
           const T vb3 = v3[kk] > T(0) ? r : -r - b3[kk];
           const T vb4 = r - mean4;
           const double u1b = 2.0 * (double)r + (double)b1[kk];
-          a.pbar[kb * 64 + lane] += T(gain * u1b + PU * (gs * (double)v1[kk] + 2.0 * gq * (double)pk[kk]));
+          a.pbar[kb * 64 + lane] += T(gain * u1b + pgs * (double)v1[kk] + pgq2 * (double)pk[kk]);
           a.bdm[(kb * 3 + 0) * 64 + lane] = -vb1;
           a.bdm[(kb * 3 + 1) * 64 + lane] = -vb3;
           a.bdm[(kb * 3 + 2) * 64 + lane] = -vb4;

@@ -141,11 +141,14 @@ bool fold_lists_fit(const TileGeom& g) {
 bool choose_tiles(Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
+  // partial sums [2][6][nw][64] (T), per-pixel FP64 sums [6][64] and coefficients [5][64], v4 stage (simplex g4)
   const size_t part = 12 * (size_t)p.nw * 64 + (p.g4s ? 2 * (size_t)p.K * 64 : 0);
-  auto fwd_lds = [&](const TileGeom& g) { return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 16; };
+  auto fwd_lds = [&](const TileGeom& g) {
+    return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 11 * 64 * 8 + 16;
+  };
   // reverse sweep: z, the solved cotangent and the accumulator over the grown tile
   auto adj_lds = [&](const TileGeom& g) {
-    return p.anw ? (3 * (size_t)p.K * g.ER * g.EC + 20 * (size_t)p.anw * 64) * p.ts + 16 : 0;
+    return p.anw ? (3 * (size_t)p.K * g.ER * g.EC + 20 * (size_t)p.anw * 64) * p.ts + 20 * 64 * 8 + 16 : 0;
   };
   auto lds_of = [&](const TileGeom& g) { return std::max(fwd_lds(g), adj_lds(g)); };
   // resident workgroups per CU allowed by the register budget of the chosen instantiation

@@ -47,21 +47,29 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int H = g.H, W = g.W;
   const bool g4s = VAR && a.g4s;
+  const gptr<const T> gz = glob(a.z);
+  const gptr<const T> gphat = glob(a.phat);
+  const gptr<T> gdm = glob(a.dm);
+  const gptr<T> gd2 = glob(a.d2);   // (h, v) pairs
 
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
   T* acc = zt + K * plane;             // [K][ER][EC] G^T(u + d) partial sums
   // [2][6][nw][64] per-class partial sums, 16-byte aligned (also read as doubles);
-  // with g4s, then [2][K][64] v4 of every class (double-buffered by step like the sums)
+  // with g4s, after the FP64 sums and coefficients, [2][K][64] v4 of every
+  // class (double-buffered by step like the sums)
   T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
-  T* v4buf = part + 2 * 6 * nw * 64;
+  // [6][64] FP64 per-pixel class sums and [5][64] FP64 per-pixel coefficients
+  double* tot = reinterpret_cast<double*>(part + 2 * 6 * nw * 64);
+  double* coef = tot + 6 * 64;
+  T* v4buf = reinterpret_cast<T*>(coef + 5 * 64);
 
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
     const int rem = idx - k * plane;
     const int er = rem / EC, ec = rem - er * EC;
     const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
-    zt[idx] = a.z[((size_t)k * H + gr) * W + gc];
+    zt[idx] = gz[((size_t)k * H + gr) * W + gc];
     acc[idx] = T(0);
   }
   __syncthreads();
@@ -78,21 +86,20 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     const size_t stepbase = ((size_t)tile * g.steps + s) * K;
 
     T Y[KPW][L][2];
-    T pk[KPW], v1[KPW], v3[KPW], v4[KPW], zcs[KPW];
+    T pk[KPW], v1[KPW], v3[KPW], v4[KPW];
     T ps = T(0), pq = T(0), psv = T(0), pa = T(0), pb = T(0), pc = T(0);
 #pragma unroll
     for (int kk = 0; kk < KPW; ++kk) {
       const int k = wid + kk * nw;
-      pk[kk] = v1[kk] = v3[kk] = v4[kk] = zcs[kk] = T(0);
+      pk[kk] = v1[kk] = v3[kk] = v4[kk] = T(0);
       if (k < K && valid) {
         const size_t kb = stepbase + k;
-        pk[kk] = a.phat[kb * 64 + lane];
-        const T d1 = a.dm[(kb * 3 + 0) * 64 + lane];
-        const T d3 = a.dm[(kb * 3 + 1) * 64 + lane];
-        const T d4 = a.dm[(kb * 3 + 2) * 64 + lane];
+        pk[kk] = gphat[kb * 64 + lane];
+        const T d1 = gdm[(kb * 3 + 0) * 64 + lane];
+        const T d3 = gdm[(kb * 3 + 1) * 64 + lane];
+        const T d4 = gdm[(kb * 3 + 2) * 64 + lane];
         const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
         const T zc = zk[0];
-        zcs[kk] = zc;
         v1[kk] = zc - d1;
         v3[kk] = zc - d3;
         v4[kk] = zc - d4;
@@ -100,13 +107,13 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         pq += pk[kk] * pk[kk];
         psv += v4[kk];
         if (g4s) v4buf[((s & 1) * K + k) * 64 + lane] = v4[kk];
-        const C2<T>* d2p = reinterpret_cast<const C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
+        const gptr<T> d2p = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
 #pragma unroll
         for (int j = 0; j < L; ++j) {
           const int dy = j / D - M, dx = j % D - M;
           const T* zr = zk + dy * EC + dx;
           const T z00 = zr[0], z01 = zr[1], z10 = zr[EC];
-          const C2<T> dd = d2p[j * 64];
+          const C2<T> dd = {d2p[j * 128], d2p[j * 128 + 1]};
           const T yh = a.c[j] * (z01 - z00) - dd.x;
           const T yv = a.c[j] * (z10 - z00) - dd.y;
           Y[kk][j][0] = yh;
@@ -117,6 +124,11 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         }
       }
     }
+    // Per-pixel sums over the classes and the per-pixel coefficients, each
+    // computed once per step: waves q < 6 reduce the q-th sum over the
+    // wavefronts in FP64, then waves 0 and 1 evaluate the two FP64 closed
+    // forms and share them through LDS (the other wavefronts would only
+    // repeat them: the per-step VALU work is what bounds this kernel).
     T* pbuf = part + (size_t)(s & 1) * 6 * nw * 64;
     pbuf[(0 * nw + wid) * 64 + lane] = ps;
     pbuf[(1 * nw + wid) * 64 + lane] = pq;
@@ -125,64 +137,82 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     pbuf[(4 * nw + wid) * 64 + lane] = pb;
     pbuf[(5 * nw + wid) * 64 + lane] = pc;
     __syncthreads();
-    if (valid) {
-    double S = 0.0, Q = 0.0, SV = 0.0, A = 0.0, B = 0.0, C = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      S += (double)pbuf[(0 * nw + w) * 64 + lane];
-      Q += (double)pbuf[(1 * nw + w) * 64 + lane];
-      SV += (double)pbuf[(2 * nw + w) * 64 + lane];
-      A += (double)pbuf[(3 * nw + w) * 64 + lane];
-      B += (double)pbuf[(4 * nw + w) * 64 + lane];
-      C += (double)pbuf[(5 * nw + w) * 64 + lane];
+#pragma unroll 1
+    for (int q = wid; q < 6; q += nw) {
+      double t = 0.0;
+#pragma unroll 1
+      for (int w = 0; w < nw; ++w) t += (double)pbuf[(q * nw + w) * 64 + lane];
+      tot[q * 64 + lane] = t;
     }
-    const double gain = data_prox_gain(S, Q, a.mu);
-    const T d4a = T(-(SV - 1.0) / (double)K);
-    // simplex g4: threshold theta with sum_k max(v4_k - theta, 0) = 1, by
-    // Michelot's active-set iteration (theta rises, the active set shrinks,
-    // at most K passes over the pixel's K values)
-    double theta = 0.0;
-    if (g4s) {
-      const T* vb = v4buf + (size_t)(s & 1) * K * 64 + lane;
-      theta = (SV - 1.0) / (double)K;
-      int cnt = K;
-      for (int it = 0; it < K; ++it) {
-        double sum = 0.0;
-        int c2 = 0;
-        for (int k = 0; k < K; ++k) {
-          const double v = (double)vb[k * 64];
-          if (v > theta) {
-            sum += v;
-            ++c2;
+    __syncthreads();
+    // the two FP64 closed forms on two different wavefronts (each keeps its
+    // own class block live, so splitting them keeps the register peak down)
+    const int wn = nw > 1 ? 1 : 0;
+    if (wid == 0 && valid) {
+      const double S = tot[0 * 64 + lane], Q = tot[1 * 64 + lane], SV = tot[2 * 64 + lane];
+      double g4c = -(SV - 1.0) / (double)K;  // affine g4: the shared d4 of the pixel
+      if (g4s) {
+        // simplex g4: threshold theta with sum_k max(v4_k - theta, 0) = 1, by
+        // Michelot's active-set iteration (theta rises, the active set
+        // shrinks, at most K passes over the pixel's K values)
+        const T* vb = v4buf + (size_t)(s & 1) * K * 64 + lane;
+        double theta = (SV - 1.0) / (double)K;
+        int cnt = K;
+        for (int it = 0; it < K; ++it) {
+          double sum = 0.0;
+          int c2 = 0;
+          for (int k = 0; k < K; ++k) {
+            const double v = (double)vb[k * 64];
+            if (v > theta) {
+              sum += v;
+              ++c2;
+            }
           }
+          if (c2 == cnt || c2 == 0) break;
+          cnt = c2;
+          theta = (sum - 1.0) / (double)c2;
         }
-        if (c2 == cnt || c2 == 0) break;
-        cnt = c2;
-        theta = (sum - 1.0) / (double)c2;
+        g4c = theta;
       }
+      coef[0 * 64 + lane] = data_prox_gain(S, Q, a.mu);
+      coef[1 * 64 + lane] = g4c;
     }
-    double n11, n12, n22;
-    schatten_multiplier<VAR>(A, B, C, a.tau, a.pkind, a.pval, n11, n12, n22);
-    const T m11 = T(n11 - 1.0), m12 = T(n12), m22 = T(n22 - 1.0);
+    if (wid == wn && valid) {
+      const double A = tot[3 * 64 + lane], B = tot[4 * 64 + lane], C = tot[5 * 64 + lane];
+      double n11, n12, n22;
+      schatten_multiplier<VAR>(A, B, C, a.tau, a.pkind, a.pval, n11, n12, n22);
+      coef[2 * 64 + lane] = n11 - 1.0;
+      coef[3 * 64 + lane] = n12;
+      coef[4 * 64 + lane] = n22 - 1.0;
+    }
+    __syncthreads();
+    if (valid) {
+    const double gain = coef[0 * 64 + lane];
+    const double g4c = coef[1 * 64 + lane];
+    const T d4a = T(g4c);
+    const double theta = g4c;
+    const T m11 = T(coef[2 * 64 + lane]), m12 = T(coef[3 * 64 + lane]), m22 = T(coef[4 * 64 + lane]);
 
 #pragma unroll
     for (int kk = 0; kk < KPW; ++kk) {
       const int k = wid + kk * nw;
       if (k < K) {
         const size_t kb = stepbase + k;
-        const T d1n = T((double)pk[kk] * gain);
+        const T d1n = T((double)gphat[kb * 64 + lane] * gain);
         const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
         const T d4n = g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
         const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
-        a.dm[(kb * 3 + 0) * 64 + lane] = d1n;
-        a.dm[(kb * 3 + 1) * 64 + lane] = d3n;
-        a.dm[(kb * 3 + 2) * 64 + lane] = d4n;
+        gdm[(kb * 3 + 0) * 64 + lane] = d1n;
+        gdm[(kb * 3 + 1) * 64 + lane] = d3n;
+        gdm[(kb * 3 + 2) * 64 + lane] = d4n;
         if (want_res) {  // primal residual: d_new - d_old = u - H z (eq. (14))
-          const double e1 = (double)d1n - (double)(zcs[kk] - v1[kk]);
-          const double e3 = (double)d3n - (double)(zcs[kk] - v3[kk]);
-          const double e4 = (double)d4n - (double)(zcs[kk] - v4[kk]);
+          const T zc = zt[k * plane + (lr + M) * EC + (lc + M)];
+          const double e1 = (double)d1n - (double)(zc - v1[kk]);
+          const double e3 = (double)d3n - (double)(zc - v3[kk]);
+          const double e4 = (double)d4n - (double)(zc - v4[kk]);
           rp_acc += e1 * e1 + e3 * e3 + e4 * e4;
         }
-        C2<T>* d2o = reinterpret_cast<C2<T>*>(a.d2) + kb * (size_t)(L * 64) + lane;
+        const gptr<T> d2o = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
         // New d2 = u2 - Y = Y (N - I) and the J^T scatter of c_j (u2 + d2).
         // The h part of offset (dy, dx) lands at (dy, dx + 1) with + and at
         // (dy, dx) with -, the v part at (dy + 1, dx) with + and at (dy, dx)
@@ -212,7 +242,8 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
               C2<T> o;
               o.x = nh;
               o.y = nv;
-              d2o[jj * 64] = o;
+              d2o[jj * 128] = o.x;
+              d2o[jj * 128 + 1] = o.y;
               if (want_res) {  // old d2 = c_j grad z - Y, rebuilt from the LDS tile
                 const T* zr = zt + k * plane + (lr + M + da) * EC + (lc + M + db);
                 const double oh = (double)(a.c[jj] * (zr[1] - zr[0]) - yh);
@@ -260,10 +291,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int w = 0; w < nw; ++w) t += red[w];
-      a.res_tile[tile] = t;
+      glob(a.res_tile)[tile] = t;
     }
   }
-  T* blk = a.acc + (size_t)tile * K * g.ER * g.EC;
+  const gptr<T> blk = glob(a.acc) + (size_t)tile * K * g.ER * g.EC;
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
     const int rem = idx - k * plane;

@@ -36,6 +36,17 @@ struct C2 {
   T x, y;
 };
 
+// Pointers held in device-side descriptor tables reach the kernels as generic
+// pointers, which the compiler turns into FLAT accesses; FLAT loads count
+// against the LDS wait counter too, so every LDS wait would also wait for
+// HBM.  Kernels re-declare them in the global address space.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> glob(T* p) {
+  return (gptr<T>)p;
+}
+
 __host__ __device__ inline int wrap_index(int x, int n) {
   int r = x % n;
   return r < 0 ? r + n : r;
