@@ -341,6 +341,7 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   {
     const int Lr = p.frow.blu ? p.frow.M : W;      // elements per row inside the transform
     long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
+    if (const char* er = std::getenv("SEGSALSA_ROWS_PER_BLOCK")) rpb = std::max(1, std::atoi(er));  // tuning runs
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
     p.rows_per_block = (int)rpb;
     fft_threads(rpb * Lr, p.row_ept, p.row_threads);
@@ -352,6 +353,8 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     while (cb < 64 && cb * 2 <= W && (long long)(cb * 2) * Lc <= cap &&
            ((long long)(cb * 2) * Lc <= 1024 || cb * 2 <= 8))
       cb *= 2;
+    if (const char* ec = std::getenv("SEGSALSA_COLS_PER_BLOCK"))  // tuning runs
+      cb = std::max(1, std::min(std::atoi(ec), W));
     p.cols_per_block = cb;
     fft_threads((long long)cb * Lc, p.col_ept, p.col_threads);
     p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
