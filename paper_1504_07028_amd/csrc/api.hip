@@ -41,8 +41,9 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // Dynamic LDS one workgroup may use (gfx950 has 160 KiB per CU).
 constexpr size_t kLdsBudget = 160 * 1024;
 
-// Factor a length into radices: 8s, then 4 and 2, 3s, 5s, then the other
-// primes in increasing order.
+// Factor a length into radices: primes above 13 (direct DFT stages) first,
+// so they run with Ns = 1 and need no inter-stage twiddles, then 8s, 4 and
+// 2, 3s, 5s, and the other primes in increasing order.
 int factorize(int N, int* rad) {
   std::vector<int> r;
   int n = N;
@@ -54,6 +55,7 @@ int factorize(int N, int* rad) {
   for (int f = 7; (long long)f * f <= n; f += 2)
     while (n % f == 0) { r.push_back(f); n /= f; }
   if (n > 1) r.push_back(n);
+  std::stable_partition(r.begin(), r.end(), [](int f) { return f > 13; });
   for (size_t i = 0; i < r.size(); ++i) rad[i] = r[i];
   return (int)r.size();
 }

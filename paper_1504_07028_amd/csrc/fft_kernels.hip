@@ -223,13 +223,41 @@ __device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int
   __syncthreads();
 }
 
-// Stockham stage of any radix R as a direct DFT: one output per work item.
+// Stockham stage of an odd radix R without a register butterfly, as a
+// direct DFT.  The stage computes, for each group j (k = j mod Ns) and output
+// q, the sum over r of x_(j + r NR) w_N^(r k stw) w_R^(q r).  The inter-stage
+// twiddles w_N^(r k stw) are applied first, once per input element and in
+// place (only when Ns > 1; the plans put these radices first); then each
+// work item forms one output from the pre-twiddled inputs, pairing the terms
+// r and R - r: with w = w_R^(q r),
+//   x_r w + x_(R-r) conj(w) = (x_r + x_(R-r)) Re w + i Im w (x_r - x_(R-r)),
+// which halves the complex multiplies.
 template <typename T, int EPT>
 __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
                               int Ns, bool inv) {
   const int NR = N / R;
   const int total = nb * N;
   const int stw = N / (Ns * R);
+  if (Ns > 1) {
+    for (int item = threadIdx.x; item < total; item += blockDim.x) {
+      int b, rem;
+      if (bs == 1) {
+        rem = item / nb;
+        b = item - rem * nb;
+      } else {
+        b = item / N;
+        rem = item - b * N;
+      }
+      const int r = rem / NR, j = rem - r * NR;
+      const int k = j % Ns;
+      if (r > 0 && k > 0) {
+        const int idx = b * bs + rem * es;
+        buf[idx] = twmul(buf[idx], tw[r * k * stw], inv);   // r k stw < R Ns stw = N
+      }
+    }
+    __syncthreads();
+  }
+  const int half = (R - 1) / 2;
   C2<T> out[EPT];
   int oi[EPT];
 #pragma unroll
@@ -247,21 +275,22 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
       }
       const int j = rem / R, q = rem - j * R;
       const int k = j % Ns;
-      const int base = b * bs;
-      const int st1 = k * stw;
-      const int st2 = q * NR;
-      int e1 = 0, e2 = 0;
-      C2<T> s = {T(0), T(0)};
-      for (int r = 0; r < R; ++r) {
-        int e = e1 + e2;
-        if (e >= N) e -= N;
-        s = cadd(s, twmul(buf[base + (j + r * NR) * es], tw[e], inv));
-        e1 += st1;
-        e2 += st2;
-        if (e2 >= N) e2 -= N;
+      const C2<T>* xj = buf + b * bs + j * es;
+      const int sr = NR * es;
+      C2<T> s = xj[0];
+      int m = 0;
+      for (int r = 1; r <= half; ++r) {
+        m += q;
+        if (m >= R) m -= R;
+        const C2<T> xa = xj[r * sr], xb = xj[(R - r) * sr];
+        const C2<T> w = tw[m * NR];
+        const T wi = inv ? -w.y : w.y;
+        const T pr = xa.x + xb.x, pi = xa.y + xb.y, dr = xa.x - xb.x, di = xa.y - xb.y;
+        s.x += pr * w.x - wi * di;
+        s.y += pi * w.x + wi * dr;
       }
       out[it] = s;
-      oi[it] = base + ((j - k) * R + k + q * Ns) * es;
+      oi[it] = b * bs + ((j - k) * R + k + q * Ns) * es;
     }
   }
   __syncthreads();
