@@ -67,7 +67,11 @@ typedef enum { SEGSALSA_FP32 = 0, SEGSALSA_FP64 = 1 } segsalsa_precision;
 
 /* One problem of eq. (7) and its SALSA parameters. */
 typedef struct {
-  int32_t K;                   /* classes, 2 <= K <= 64                                         */
+  int32_t K;                   /* classes, 2 <= K <= 64; each workgroup keeps every class of its
+                                  pixels in registers, so larger patches allow fewer classes
+                                  (else UNSUPPORTED): FP32 K <= 64 for M <= 1, 32 for M = 2,
+                                  16 for M >= 3; FP64 K <= 64 for M = 0, 32 for M = 1, 16 for
+                                  M >= 2                                                          */
   int32_t H, W;                /* image rows and columns, 1 <= H, W <= 4096, H*W >= 2           */
   int32_t patch_radius;        /* M in [0, 5]: (2M+1) x (2M+1) patch, L = (2M+1)^2 (Sec. 3)     */
   const double *patch_weights; /* HOST, L finite multipliers c_j of P_j (eq. (4)), row-major in

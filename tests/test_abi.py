@@ -201,3 +201,17 @@ def test_g4_simplex_flag(S):
     assert S.lib().segsalsa_str_workspace_size(ctypes.byref(s), 0, ctypes.byref(n)) == INVALID
     assert grad_size(S, base_problem(S, g4_simplex=True), 5)[0] == UNSUPPORTED
     assert grad_size(S, base_problem(S, schatten_p=3.0), 5)[0] == UNSUPPORTED
+
+
+def test_shapes_beyond_one_workgroup_are_unsupported(S):
+    """Large K with a large patch needs more registers than one workgroup holds (documented envelope)."""
+    st, _ = status_of_size(S, base_problem(S, K=64, H=20, W=20, patch_radius=5, patch_weights=[1.0] * 121))
+    assert st == UNSUPPORTED
+    assert status_of_size(S, base_problem(S, K=64, H=20, W=20))[0] == OK            # FP32, 3x3
+    assert status_of_size(S, base_problem(S, K=64, H=20, W=20), prec=1)[0] == UNSUPPORTED
+    assert status_of_size(S, base_problem(S, K=32, H=20, W=20), prec=1)[0] == OK
+    pw25 = dict(patch_radius=2, patch_weights=[1.0] * 25)
+    assert status_of_size(S, base_problem(S, K=32, H=20, W=20, **pw25))[0] == OK
+    assert status_of_size(S, base_problem(S, K=33, H=20, W=20, **pw25))[0] == UNSUPPORTED
+    assert status_of_size(S, base_problem(S, K=16, H=20, W=20, **pw25), prec=1)[0] == OK
+    assert status_of_size(S, base_problem(S, K=17, H=20, W=20, **pw25), prec=1)[0] == UNSUPPORTED

@@ -106,3 +106,31 @@ def test_lambda_zero_identity_prox():
     z, *_ = gpu_solve(S, probs, c, 1, 1.0, 0.0, 0.5, 7, torch.float64)
     zo = oracle_solve(probs, c, 1, 1.0, 0.0, 0.5, 7)
     assert np.max(np.abs(z.cpu().numpy() - zo)) <= FP64_TOL
+
+
+# edges of the interface: the most classes (K = 64), an odd K above 32 (17 class pairs), the longest
+# sides (4096 = 8^4 transforms) in both orientations; FP32 also at the largest K its register budget
+# allows with a 3x3 (K = 64) and a 5x5 patch (K = 32)
+EDGE_CASES = [
+    (5, 6, 64, 0, 1.0, 4, None),
+    (9, 11, 33, 0, 1.0, 3, None),
+    (4096, 3, 2, 0, 2.0, 3, None),
+    (3, 4096, 3, 1, math.inf, 3, None),
+    (5, 6, 64, 1, 1.0, 4, torch.float32),
+    (7, 9, 32, 2, 1.0, 3, torch.float32),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("H,W,K,M,p,iters,only", EDGE_CASES)
+def test_interface_edges(H, W, K, M, p, iters, only, dtype):
+    if only is not None and dtype != only:
+        pytest.skip("beyond the FP64 register budget of one workgroup (UNSUPPORTED by design)")
+    S = need_gpu()
+    say(f"case edge H={H} W={W} K={K} M={M} p={p} iters={iters} {dtype}")
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=H * 17 + W * 3 + K)
+    z, *_ = gpu_solve(S, probs, c, M, p, 0.8, 1.3, iters, dtype)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
