@@ -716,8 +716,9 @@ hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStrea
   {
     PhaseTimer t0(0, st);
     for (const auto& g : ls.groups) {
+      // checked rounds (residuals) run the instantiation that accumulates them
       e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.lds,
-                      b.c.pkind == kSchattenP || b.c.g4s, st);
+                      b.c.pkind == kSchattenP || b.c.g4s || residuals, st);
       if (e != hipSuccess) return e;
     }
     t0.stop();

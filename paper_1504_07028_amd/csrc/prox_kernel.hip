@@ -27,8 +27,9 @@
 
 namespace segsalsa {
 
-// VAR compiles in the method's variants (general Schatten p, simplex g4);
-// the plain instantiation (p in {1, 2, inf}, affine g4) stays lean.
+// VAR compiles in the method's variants (general Schatten p, simplex g4) and
+// the primal-residual accumulation of checked rounds; the plain instantiation
+// (p in {1, 2, inf}, affine g4, no residuals) stays lean.
 template <typename T, int M, int KPW, bool VAR>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
@@ -76,7 +77,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
 
   const int P = th * tw;
   const int nsteps = (P + 63) >> 6;
-  const bool want_res = a.res_tile != nullptr;
+  const bool want_res = VAR && a.res_tile != nullptr;  // checked rounds use the VAR instantiation
   double rp_acc = 0.0;
   for (int s = 0; s < nsteps; ++s) {
     const int f = (s << 6) + lane;

@@ -37,7 +37,8 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
 }
 
 // Per-round launches over a table of per-image descriptors in device memory.
-// variants: the instantiation with the general Schatten p and the simplex g4 compiled in
+// variants: the instantiation with the general Schatten p, the simplex g4 and the
+// primal-residual accumulation compiled in (required for descriptors with res_tile set)
 hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
                        bool variants, hipStream_t st);
 hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,

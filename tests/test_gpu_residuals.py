@@ -63,6 +63,8 @@ def test_stopping_rule_stops_where_the_oracle_does():
     say(f"  gpu stopped after {st['rounds_done']} rounds, oracle after {first}")
     assert st["rounds_done"] == first < iters
     assert st["primal_res"] <= tol and st["dual_res"] <= tol
-    # the stopped run equals a fixed-round run of the same length, bit for bit
+    # the stopped run equals a fixed-round run of the same length (to rounding: its checked rounds
+    # run the kernel instantiation that also accumulates the residuals, whose floating-point
+    # contractions may differ in the last bit)
     z2, _ = solve_stats(S, probs, c, M, 1.0, 0.5, 2.0, st["rounds_done"], torch.float64, 0)
-    assert torch.equal(z, z2)
+    assert float(torch.max(torch.abs(z - z2))) <= 1e-13
