@@ -61,12 +61,16 @@ int factorize(int N, int* rad) {
 }
 
 // Largest prime factor handled by a direct DFT stage; longer primes go
-// through Bluestein (SEGSALSA_BLUESTEIN_PRIME overrides, for tuning).
+// through Bluestein (SEGSALSA_BLUESTEIN_PRIME overrides, for tuning).  The
+// paired direct stage costs (R - 1) / 2 complex updates per output; a
+// Bluestein transform costs two power-of-two transforms of length >= 2N - 1:
+// measured, a direct 61-point stage runs the 610-long columns in half the
+// time of Bluestein (length 2048).
 int bluestein_prime() {
   static int v = -1;
   if (v < 0) {
     const char* e = std::getenv("SEGSALSA_BLUESTEIN_PRIME");
-    v = e ? std::max(5, std::atoi(e)) : 40;
+    v = e ? std::max(5, std::atoi(e)) : 100;
   }
   return v;
 }
@@ -345,6 +349,10 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
     if (const char* er = std::getenv("SEGSALSA_ROWS_PER_BLOCK")) rpb = std::max(1, std::atoi(er));  // tuning runs
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
+    // one workgroup holds at most kFftEptMax elements per thread of kFftMaxThreads, and its LDS
+    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads ||
+                       ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs > kLdsBudget))
+      --rpb;
     p.rows_per_block = (int)rpb;
     fft_threads(rpb * Lr, p.row_ept, p.row_threads);
     p.row_lds = ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
@@ -357,6 +365,9 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
       cb *= 2;
     if (const char* ec = std::getenv("SEGSALSA_COLS_PER_BLOCK"))  // tuning runs
       cb = std::max(1, std::min(std::atoi(ec), W));
+    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * kFftMaxThreads ||
+                      ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs > kLdsBudget))
+      --cb;
     p.cols_per_block = cb;
     fft_threads((long long)cb * Lc, p.col_ept, p.col_threads);
     p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;

@@ -28,9 +28,10 @@ SMALL_CASES = [
     (29, 131, 9, 2, 1.0, 6),
     (70, 33, 16, 1, math.inf, 5),
     (37, 41, 7, 3, 2.0, 4),
-    (47, 53, 4, 1, 1.0, 5),      # both sides prime > 40: Bluestein rows and columns
-    (97, 509, 3, 1, 1.0, 4),     # Bluestein with M = 1024
+    (47, 53, 4, 1, 1.0, 5),      # both sides prime: direct 47- and 53-point stages
+    (97, 509, 3, 1, 1.0, 4),     # a direct 97-point stage; Bluestein (M = 1024) for 509
     (122, 86, 5, 2, math.inf, 4),  # 2 x 61 and 2 x 43
+    (211, 101, 2, 1, 1.0, 3),    # primes just above the direct-stage limit: Bluestein both ways
 ]
 
 
