@@ -87,7 +87,9 @@ typedef struct {
   int32_t residual_every;      /* > 0: compute the primal and dual residuals after every
                                   residual_every-th round and after the last one, report the last
                                   ones and the objective in stats (needs a HOST stats pointer);
-                                  each checked round waits for the stream                        */
+                                  each checked round waits for the stream.  Checked rounds run a
+                                  build of the proximity kernel that also sums the residuals, so
+                                  their rounding may differ from unchecked rounds in the last bit */
   double tol;                  /* > 0: stop after the first checked round whose primal and dual
                                   residuals are both <= tol (the paper's stopping rule, Sec. 4);
                                   needs residual_every > 0.  0: run exactly `iters` rounds        */
