@@ -4,7 +4,9 @@
   multipliers) equal the FP64 reference gradient (PyTorch CPU autograd of the
   oracle-equivalent rounds, itself pinned to finite differences of the numpy
   oracle) within 1e-9 relative to the largest entry, for p in {1, 2, inf},
-  M in {0, 1, 2}, probabilities and logits, lambda = 0.
+  M in {0, 1, 2}, probabilities and logits, lambda = 0, and K up to 16 (one,
+  two and four classes per wavefront in the reverse-sweep kernel); the FP32
+  gradients within 1e-3 of the reference on the same inputs.
 * The checkpoint interval changes nothing (bitwise); the checkpointed forward
   returns the same z as segsalsa_str_solve (bitwise); zero rounds.
 * The 256x256, K = 8, 3x3 patch, 50-round workload: central finite
@@ -65,6 +67,8 @@ CASES = [
     (29, 31, 3, 0, 1.0, 0.5, 1.0, 9, False),
     (26, 34, 4, 2, 1.0, 0.9, 1.7, 8, True),
     (31, 27, 5, 1, 1.0, 0.0, 1.2, 8, True),
+    (20, 24, 11, 1, 1.0, 0.7, 1.4, 5, True),     # two (FP32) or four (FP64) classes per wavefront, last one padded
+    (18, 22, 16, 2, math.inf, 0.9, 1.6, 4, False),  # four classes per wavefront (the paper's K and patch)
 ]
 
 
@@ -87,16 +91,21 @@ def test_fp64_gradient_matches_reference(case):
     assert el <= 1e-9 or (lam == 0.0 and abs(gl - glr) <= 1e-9 * max(1.0, abs(glr)))
 
 
-def test_fp32_gradient_near_reference():
+FP32_CASES = [CASES[0], CASES[-2], CASES[-1]]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[f"{c[0]}x{c[1]}_k{c[2]}_m{c[3]}" for c in FP32_CASES])
+def test_fp32_gradient_near_reference(case):
     S = need_gpu()
-    H, W, K, M, p, lam, mu, iters, logits = CASES[0]
-    _, lg, _ = synth.make_image(H, W, K, 500 + H, 1.0, 1.5)
+    H, W, K, M, p, lam, mu, iters, logits = case
+    probs, lg, _ = synth.make_image(H, W, K, 500 + H, 1.0, 1.5)
+    x32 = (lg if logits else probs).astype(np.float32).astype(np.float64)
     c = synth.gaussian_patch_multipliers(M, 1.0)
-    w = np.random.default_rng(H * W).standard_normal((K, H, W))
-    lg32 = lg.astype(np.float32).astype(np.float64)
+    w32 = np.random.default_rng(H * W).standard_normal((K, H, W)).astype(np.float32).astype(np.float64)
     c32 = np.asarray(c, dtype=np.float32).astype(np.float64)
-    _, gi, gl, gw = gpu_grad(S, lg32, w, c32, M, p, lam, mu, iters, logits, dtype=torch.float32)
-    _, gxr, glr, gwr = ref_grad(lg32, w.astype(np.float32).astype(np.float64), c32, M, p, lam, mu, iters, logits)
+    say(f"case {case} FP32")
+    _, gi, gl, gw = gpu_grad(S, x32, w32, c32, M, p, lam, mu, iters, logits, dtype=torch.float32)
+    _, gxr, glr, gwr = ref_grad(x32, w32, c32, M, p, lam, mu, iters, logits)
     ex, el, ew = rel(gi.double().cpu().numpy(), gxr), abs(gl - glr) / abs(glr), rel(gw, gwr)
     say(f"  FP32: grad_input {ex:.1e}  grad_lambda {el:.1e}  grad_weights {ew:.1e}")
     assert ex <= 1e-3 and el <= 1e-3 and ew <= 1e-3
