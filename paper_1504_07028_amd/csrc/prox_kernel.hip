@@ -140,8 +140,8 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     __syncthreads();
 #pragma unroll 1
     for (int q = wid; q < 6; q += nw) {
-      double t = 0.0;
-#pragma unroll 1
+      double t = 0.0;  // fixed order w = 0, 1, ...; unrolled so the LDS reads overlap
+#pragma unroll 4
       for (int w = 0; w < nw; ++w) t += (double)pbuf[(q * nw + w) * 64 + lane];
       tot[q * 64 + lane] = t;
     }
