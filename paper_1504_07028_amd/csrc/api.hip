@@ -203,12 +203,12 @@ bool choose_tiles(Plan& p) {
 // Elements per thread (2, 4, 8 or 16) and workgroup size of an LDS FFT
 // workgroup holding `items` complex elements: the fewest elements per thread
 // that keep the workgroup within 1024 threads.
-void fft_threads(long long items, int& ept, int& threads) {
+void fft_threads(long long items, int max_threads, int& ept, int& threads) {
   ept = 2;
-  while (ept < kFftEptMax && (items + ept - 1) / ept > kFftMaxThreads) ept *= 2;
+  while (ept < kFftEptMax && (items + ept - 1) / ept > max_threads) ept *= 2;
   long long t = (items + ept - 1) / ept;
   t = (t + 63) / 64 * 64;
-  threads = (int)std::max<long long>(64, std::min<long long>(t, kFftMaxThreads));
+  threads = (int)std::max<long long>(64, std::min<long long>(t, max_threads));
 }
 
 // ---------------------------------------------------------------------------
@@ -340,6 +340,7 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   // thread for latency hiding, whole rows (columns) plus the twiddle table in
   // LDS; column blocks of 8+ columns on tall images for coalesced rows.
   const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
+  const int fmax = fft_max_threads_rt(p.fp64);   // FFT workgroup size limit of this precision
   // Bluestein needs scratch next to the data; where that exceeds LDS, keep
   // the direct stages
   if (p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
@@ -349,12 +350,12 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
     if (const char* er = std::getenv("SEGSALSA_ROWS_PER_BLOCK")) rpb = std::max(1, std::atoi(er));  // tuning runs
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
-    // one workgroup holds at most kFftEptMax elements per thread of kFftMaxThreads, and its LDS
-    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads ||
+    // one workgroup holds at most kFftEptMax elements per thread of fmax, and its LDS
+    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * fmax ||
                        ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs > kLdsBudget))
       --rpb;
     p.rows_per_block = (int)rpb;
-    fft_threads(rpb * Lr, p.row_ept, p.row_threads);
+    fft_threads(rpb * Lr, fmax, p.row_ept, p.row_threads);
     p.row_lds = ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
   }
   {
@@ -365,11 +366,11 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
       cb *= 2;
     if (const char* ec = std::getenv("SEGSALSA_COLS_PER_BLOCK"))  // tuning runs
       cb = std::max(1, std::min(std::atoi(ec), W));
-    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * kFftMaxThreads ||
+    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * fmax ||
                       ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs > kLdsBudget))
       --cb;
     p.cols_per_block = cb;
-    fft_threads((long long)cb * Lc, p.col_ept, p.col_threads);
+    fft_threads((long long)cb * Lc, fmax, p.col_ept, p.col_threads);
     p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
   }
   const size_t nt = (size_t)p.g.ntiles();
@@ -672,8 +673,9 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     ls.row_lds = std::max(ls.row_lds, p.row_lds);
     ls.col_lds = std::max(ls.col_lds, p.col_lds);
   }
-  ls.row_threads = std::min(kFftMaxThreads, (ls.row_threads + 63) / 64 * 64);
-  ls.col_threads = std::min(kFftMaxThreads, (ls.col_threads + 63) / 64 * 64);
+  const int fmax = fft_max_threads<T>();
+  ls.row_threads = std::min(fmax, (ls.row_threads + 63) / 64 * 64);
+  ls.col_threads = std::min(fmax, (ls.col_threads + 63) / 64 * 64);
   ls.row_blocks = rb;
   ls.col_blocks = cb;
   hipError_t e;

@@ -428,7 +428,7 @@ hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftMaxThreads) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(kFftMaxThreads) fft_rows_fwd_kernel(const RowF
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftMaxThreads) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(fft_max_threads<T>()) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const ColArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(kFftMaxThreads) fft_cols_kernel(const ColArgs<
 }
 
 template <typename T, int EPT>
-__global__ void __launch_bounds__(kFftMaxThreads) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowInvArgs<T>& a = descs[find_desc(descs, ndesc)];
