@@ -104,8 +104,10 @@ struct Plan {
   size_t adj_lds;
   FftPlanDev frow, fcol;
   int rows_per_block, row_threads, row_ept;
+  int row_threads_n, row_ept_n;  // FP64 narrow sizing (at most kFftNarrowThreads threads), 0 if it does not fit
   size_t row_lds;
   int cols_per_block, col_threads, col_ept;
+  int col_threads_n, col_ept_n;
   size_t col_lds;
   // workspace offsets (bytes)
   size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_frow, off_fcol, off_phat, off_dm, off_d2, off_acc, off_spec,
@@ -340,7 +342,6 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   // thread for latency hiding, whole rows (columns) plus the twiddle table in
   // LDS; column blocks of 8+ columns on tall images for coalesced rows.
   const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
-  const int fmax = fft_max_threads_rt(p.fp64);   // FFT workgroup size limit of this precision
   // Bluestein needs scratch next to the data; where that exceeds LDS, keep
   // the direct stages
   if (p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
@@ -350,12 +351,15 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
     if (const char* er = std::getenv("SEGSALSA_ROWS_PER_BLOCK")) rpb = std::max(1, std::atoi(er));  // tuning runs
     rpb = std::max<long long>(1, std::min<long long>(rpb, H));
-    // one workgroup holds at most kFftEptMax elements per thread of fmax, and its LDS
-    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * fmax ||
+    // one workgroup holds at most kFftEptMax elements per thread of kFftMaxThreads, and its LDS
+    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads ||
                        ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs > kLdsBudget))
       --rpb;
     p.rows_per_block = (int)rpb;
-    fft_threads(rpb * Lr, fmax, p.row_ept, p.row_threads);
+    fft_threads(rpb * Lr, kFftMaxThreads, p.row_ept, p.row_threads);
+    p.row_ept_n = p.row_threads_n = 0;
+    if (p.fp64 && rpb * Lr <= (long long)kFftEptMax * kFftNarrowThreads)
+      fft_threads(rpb * Lr, kFftNarrowThreads, p.row_ept_n, p.row_threads_n);
     p.row_lds = ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
   }
   {
@@ -366,11 +370,14 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
       cb *= 2;
     if (const char* ec = std::getenv("SEGSALSA_COLS_PER_BLOCK"))  // tuning runs
       cb = std::max(1, std::min(std::atoi(ec), W));
-    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * fmax ||
+    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * kFftMaxThreads ||
                       ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs > kLdsBudget))
       --cb;
     p.cols_per_block = cb;
-    fft_threads((long long)cb * Lc, fmax, p.col_ept, p.col_threads);
+    fft_threads((long long)cb * Lc, kFftMaxThreads, p.col_ept, p.col_threads);
+    p.col_ept_n = p.col_threads_n = 0;
+    if (p.fp64 && (long long)cb * Lc <= (long long)kFftEptMax * kFftNarrowThreads)
+      fft_threads((long long)cb * Lc, kFftNarrowThreads, p.col_ept_n, p.col_threads_n);
     p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
   }
   const size_t nt = (size_t)p.g.ntiles();
@@ -405,10 +412,11 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     if (lg[0] == '1')
       std::fprintf(stderr,
                    "[segsalsa] plan %s K=%d H=%d W=%d M=%d: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
-                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d; cols/block=%d threads=%d ept=%d; region %zu B\n",
+                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d (narrow %d x %d); cols/block=%d threads=%d "
+                   "ept=%d (narrow %d x %d); region %zu B\n",
                    p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.g.ntr, p.g.ntc, p.g.TR, p.g.TC, p.g.ntiles(), p.g.steps,
-                   p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.cols_per_block,
-                   p.col_threads, p.col_ept, p.total);
+                   p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.row_threads_n, p.row_ept_n,
+                   p.cols_per_block, p.col_threads, p.col_ept, p.col_threads_n, p.col_ept_n, p.total);
   }
   return SEGSALSA_OK;
 }
@@ -538,6 +546,7 @@ struct LaunchSet {
   std::vector<Group> groups;
   int nact = 0;
   int row_blocks = 0, row_threads = 64, row_ept = 2, col_blocks = 0, col_threads = 64, col_ept = 2;
+  bool row_narrow = false, col_narrow = false;  // FP64: the 512-thread FFT instantiations
   size_t row_lds = 0, col_lds = 0;
 };
 
@@ -673,9 +682,38 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     ls.row_lds = std::max(ls.row_lds, p.row_lds);
     ls.col_lds = std::max(ls.col_lds, p.col_lds);
   }
-  const int fmax = fft_max_threads<T>();
-  ls.row_threads = std::min(fmax, (ls.row_threads + 63) / 64 * 64);
-  ls.col_threads = std::min(fmax, (ls.col_threads + 63) / 64 * 64);
+  ls.row_threads = std::min(kFftMaxThreads, (ls.row_threads + 63) / 64 * 64);
+  ls.col_threads = std::min(kFftMaxThreads, (ls.col_threads + 63) / 64 * 64);
+  if (sizeof(T) == 8) {
+    // FP64: the narrow (512-thread, spill-free) FFT kernels where they measured
+    // faster.  Rows: for a single image (latency-bound passes); a batch keeps
+    // the occupancy of the wide kernels.  Columns: unless they would need more
+    // than 4 elements per thread where the wide sizing stays below 1024 threads.
+    if (active.size() == 1 && b.im[active[0]].plan.row_threads_n > 0) {
+      const Plan& p = b.im[active[0]].plan;
+      ls.row_ept = p.row_ept_n;
+      ls.row_threads = p.row_threads_n;
+      ls.row_narrow = true;
+    }
+    bool fits = true;
+    int ept_n = 2;
+    for (const int i : active) {
+      const Plan& p = b.im[i].plan;
+      if (p.col_threads_n == 0) fits = false;
+      ept_n = std::max(ept_n, p.col_ept_n);
+    }
+    if (fits && (ept_n <= 4 || ls.col_threads == kFftMaxThreads)) {
+      int thr = 64;
+      for (const int i : active) {
+        const Plan& p = b.im[i].plan;
+        const long long citems = (long long)p.cols_per_block * (p.fcol.blu ? p.fcol.M : p.H);
+        thr = std::max<int>(thr, (int)((citems + ept_n - 1) / ept_n));
+      }
+      ls.col_ept = ept_n;
+      ls.col_threads = std::min(kFftNarrowThreads, (thr + 63) / 64 * 64);
+      ls.col_narrow = true;
+    }
+  }
   ls.row_blocks = rb;
   ls.col_blocks = cb;
   hipError_t e;
@@ -706,17 +744,17 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
   hipError_t e;
   PhaseTimer t1(1, st);
   e = launch_rows_fwd(wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_lds, st);
+                      ls.row_narrow, ls.row_lds, st);
   t1.stop();
   if (e != hipSuccess) return e;
   PhaseTimer t2(2, st);
-  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads, ls.col_lds,
-                  st);
+  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads,
+                  ls.col_narrow, ls.col_lds, st);
   t2.stop();
   if (e != hipSuccess) return e;
   PhaseTimer t3(3, st);
   e = launch_rows_inv(wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_lds, st);
+                      ls.row_narrow, ls.row_lds, st);
   t3.stop();
   return e;
 }

@@ -427,8 +427,8 @@ hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab
   return launch_bluestein_table_t(p, tab, bf, st);
 }
 
-template <typename T, int EPT>
-__global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
+template <typename T, int EPT, int MAXT>
+__global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -470,8 +470,8 @@ __global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_fwd_kernel(cons
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) out[idx] = buf[idx];
 }
 
-template <typename T, int EPT>
-__global__ void __launch_bounds__(fft_max_threads<T>()) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
+template <typename T, int EPT, int MAXT>
+__global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const ColArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -506,8 +506,8 @@ __global__ void __launch_bounds__(fft_max_threads<T>()) fft_cols_kernel(const Co
   }
 }
 
-template <typename T, int EPT>
-__global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
+template <typename T, int EPT, int MAXT>
+__global__ void __launch_bounds__(MAXT) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
   const RowInvArgs<T>& a = descs[find_desc(descs, ndesc)];
@@ -535,39 +535,48 @@ __global__ void __launch_bounds__(fft_max_threads<T>()) fft_rows_inv_kernel(cons
   }
 }
 
-template <typename K, typename A>
-static hipError_t launch_fft(K fn, const A* descs, int ndesc, int blocks, int threads, size_t lds, hipStream_t st) {
-  static bool lds_set = false;  // one static per kernel instantiation; idempotent
+// One "LDS limit raised" flag per kernel instantiation (FN is the kernel).
+template <auto FN, typename A>
+static hipError_t launch_fft(const A* descs, int ndesc, int blocks, int threads, size_t lds, hipStream_t st) {
+  static bool lds_set = false;  // idempotent, so a racing second call is harmless
   if (!lds_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(FN),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMax);
     if (e != hipSuccess) return e;
     lds_set = true;
   }
-  hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, st, descs, ndesc);
+  hipLaunchKernelGGL(FN, dim3(blocks), dim3(threads), lds, st, descs, ndesc);
   return hipGetLastError();
 }
 
-template <typename A, typename F2, typename F4, typename F8, typename F16>
-static hipError_t launch_ept(int ept, F2 f2, F4 f4, F8 f8, F16 f16, const A* d, int n, int blocks, int threads,
-                             size_t lds, hipStream_t st) {
+template <auto F2, auto F4, auto F8, auto F16, typename A>
+static hipError_t launch_ept(int ept, const A* d, int n, int blocks, int threads, size_t lds, hipStream_t st) {
   switch (ept) {
-    case 2: return launch_fft(f2, d, n, blocks, threads, lds, st);
-    case 4: return launch_fft(f4, d, n, blocks, threads, lds, st);
-    case 8: return launch_fft(f8, d, n, blocks, threads, lds, st);
-    case 16: return launch_fft(f16, d, n, blocks, threads, lds, st);
+    case 2: return launch_fft<F2>(d, n, blocks, threads, lds, st);
+    case 4: return launch_fft<F4>(d, n, blocks, threads, lds, st);
+    case 8: return launch_fft<F8>(d, n, blocks, threads, lds, st);
+    case 16: return launch_fft<F16>(d, n, blocks, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-#define SEG_FFT_LAUNCHER(NAME, ARGS, KERNEL)                                                                     \
-  hipError_t NAME(const ARGS<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st) {     \
-    return launch_ept(ept, KERNEL<float, 2>, KERNEL<float, 4>, KERNEL<float, 8>, KERNEL<float, 16>, d, n, blocks, \
-                      threads, lds, st);                                                                          \
-  }                                                                                                               \
-  hipError_t NAME(const ARGS<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st) {    \
-    return launch_ept(ept, KERNEL<double, 2>, KERNEL<double, 4>, KERNEL<double, 8>, KERNEL<double, 16>, d, n,     \
-                      blocks, threads, lds, st);                                                                  \
+#define SEG_FFT_LAUNCHER(NAME, ARGS, KERNEL)                                                                       \
+  hipError_t NAME(const ARGS<float>* d, int n, int blocks, int ept, int threads, bool, size_t lds, hipStream_t st) { \
+    return launch_ept<KERNEL<float, 2, kFftMaxThreads>, KERNEL<float, 4, kFftMaxThreads>,                           \
+                      KERNEL<float, 8, kFftMaxThreads>, KERNEL<float, 16, kFftMaxThreads>>(ept, d, n, blocks,       \
+                                                                                            threads, lds, st);      \
+  }                                                                                                                 \
+  hipError_t NAME(const ARGS<double>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,           \
+                  hipStream_t st) {                                                                                 \
+    if (narrow) {                                                                                                   \
+      if (threads > kFftNarrowThreads) return hipErrorInvalidValue;                                                 \
+      return launch_ept<KERNEL<double, 2, kFftNarrowThreads>, KERNEL<double, 4, kFftNarrowThreads>,                 \
+                        KERNEL<double, 8, kFftNarrowThreads>, KERNEL<double, 16, kFftNarrowThreads>>(               \
+          ept, d, n, blocks, threads, lds, st);                                                                     \
+    }                                                                                                               \
+    return launch_ept<KERNEL<double, 2, kFftMaxThreads>, KERNEL<double, 4, kFftMaxThreads>,                         \
+                      KERNEL<double, 8, kFftMaxThreads>, KERNEL<double, 16, kFftMaxThreads>>(ept, d, n, blocks,     \
+                                                                                              threads, lds, st);    \
   }
 
 SEG_FFT_LAUNCHER(launch_rows_fwd, RowFwdArgs, fft_rows_fwd_kernel)

@@ -28,13 +28,10 @@ constexpr int kMaxK = 64;
 constexpr int kMaxSide = 4096;
 constexpr int kFftEptMax = 16;     // most complex elements per thread in one LDS FFT workgroup
 constexpr int kFftMaxThreads = 1024;  // FFT workgroup size limit
-// FP64 FFT workgroups stop at 512 threads: under a 1024-thread launch bound
-// the FP64 transforms are held to 128 VGPRs and spill; at 512 they get 256.
-template <typename T>
-__host__ __device__ constexpr int fft_max_threads() {
-  return sizeof(T) == 8 ? 512 : kFftMaxThreads;
-}
-inline int fft_max_threads_rt(bool fp64) { return fp64 ? fft_max_threads<double>() : fft_max_threads<float>(); }
+// FP64 FFT kernels also come built for workgroups of at most 512 threads
+// ("narrow"): under the 1024-thread launch bound the FP64 transforms are held
+// to 128 VGPRs and spill, under 512 they get 256 (at half the occupancy).
+constexpr int kFftNarrowThreads = 512;
 constexpr int kMaxRadices = 24;
 constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
 

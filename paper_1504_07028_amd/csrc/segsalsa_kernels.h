@@ -44,12 +44,20 @@ hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads,
 hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
                        bool variants, hipStream_t st);
 
-hipError_t launch_rows_fwd(const RowFwdArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_fwd(const RowFwdArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_cols(const ColArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<float>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
-hipError_t launch_rows_inv(const RowInvArgs<double>* d, int n, int blocks, int ept, int threads, size_t lds, hipStream_t st);
+// FFT passes; narrow (FP64 only): the instantiation built for at most 512
+// threads per workgroup (threads must not exceed it)
+hipError_t launch_rows_fwd(const RowFwdArgs<float>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
+hipError_t launch_rows_fwd(const RowFwdArgs<double>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
+hipError_t launch_cols(const ColArgs<float>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
+hipError_t launch_cols(const ColArgs<double>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<float>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
+hipError_t launch_rows_inv(const RowInvArgs<double>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
+                           hipStream_t st);
 
 // Set-up, initialisation and data-movement kernels (misc_kernels.hip).
 template <typename T>
