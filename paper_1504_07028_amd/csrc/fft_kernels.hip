@@ -228,10 +228,11 @@ __device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int
 // q, the sum over r of x_(j + r NR) w_N^(r k stw) w_R^(q r).  The inter-stage
 // twiddles w_N^(r k stw) are applied first, once per input element and in
 // place (only when Ns > 1; the plans put these radices first); then each
-// work item forms one output from the pre-twiddled inputs, pairing the terms
-// r and R - r: with w = w_R^(q r),
+// work item forms the outputs q and R - q from the pre-twiddled inputs,
+// pairing the terms r and R - r: with w = w_R^(q r),
 //   x_r w + x_(R-r) conj(w) = (x_r + x_(R-r)) Re w + i Im w (x_r - x_(R-r)),
-// which halves the complex multiplies.
+// and output R - q takes conj(w) in place of w, which halves the complex
+// multiplies and the LDS reads.
 template <typename T, int EPT>
 __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
                               int Ns, bool inv) {
@@ -257,27 +258,37 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
     }
     __syncthreads();
   }
+  // One item per output pair (q, R - q) of a butterfly (q = 0 alone): both
+  // outputs take the same pair sums x_r + x_(R-r), x_r - x_(R-r) against
+  // conjugate twiddles, so the inputs are read once for two outputs.  R is an
+  // odd prime >= 17 here (smaller radices have their own stages), so the
+  // nb * N * (R + 1) / (2 R) <= 9/17 nb * N items fit in EPT / 2 + 1 per
+  // thread whenever nb * N <= EPT * blockDim.x.
+  constexpr int EPTP = EPT / 2 + 1;
   const int half = (R - 1) / 2;
-  C2<T> out[EPT];
-  int oi[EPT];
+  const int H1 = half + 1;
+  const int ptotal = nb * NR * H1;
+  C2<T> oa[EPTP], ob[EPTP];
+  int ia[EPTP], ib[EPTP];
 #pragma unroll
-  for (int it = 0; it < EPT; ++it) {
+  for (int it = 0; it < EPTP; ++it) {
     const int item = threadIdx.x + it * blockDim.x;
-    oi[it] = -1;
-    if (item < total) {
+    ia[it] = ib[it] = -1;
+    if (item < ptotal) {
       int b, rem;
       if (bs == 1) {
         rem = item / nb;
         b = item - rem * nb;
       } else {
-        b = item / N;
-        rem = item - b * N;
+        b = item / (NR * H1);
+        rem = item - b * (NR * H1);
       }
-      const int j = rem / R, q = rem - j * R;
+      const int j = rem / H1, q = rem - j * H1;
       const int k = j % Ns;
       const C2<T>* xj = buf + b * bs + j * es;
       const int sr = NR * es;
-      C2<T> s = xj[0];
+      const C2<T> x0 = xj[0];
+      C2<T> s = x0, t = x0;   // outputs q and R - q
       int m = 0;
       for (int r = 1; r <= half; ++r) {
         m += q;
@@ -288,15 +299,24 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
         const T pr = xa.x + xb.x, pi = xa.y + xb.y, dr = xa.x - xb.x, di = xa.y - xb.y;
         s.x += pr * w.x - wi * di;
         s.y += pi * w.x + wi * dr;
+        t.x += pr * w.x + wi * di;
+        t.y += pi * w.x - wi * dr;
       }
-      out[it] = s;
-      oi[it] = b * bs + ((j - k) * R + k + q * Ns) * es;
+      const int base = b * bs + ((j - k) * R + k) * es;
+      oa[it] = s;
+      ia[it] = base + q * Ns * es;
+      if (q > 0) {
+        ob[it] = t;
+        ib[it] = base + (R - q) * Ns * es;
+      }
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int it = 0; it < EPT; ++it)
-    if (oi[it] >= 0) buf[oi[it]] = out[it];
+  for (int it = 0; it < EPTP; ++it) {
+    if (ia[it] >= 0) buf[ia[it]] = oa[it];
+    if (ib[it] >= 0) buf[ib[it]] = ob[it];
+  }
   __syncthreads();
 }
 
