@@ -465,24 +465,34 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   // right-hand side = sum of the grown-tile partial sums covering (r, c)
   const size_t plane = (size_t)a.g.ER * a.g.EC;
   const bool has1 = k1 < a.K;
-  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
-    const int rr = idx / W, c = idx - rr * W;
-    const int* rl = a.frow + (size_t)(row0 + rr) * kFoldStride;
-    const int* cl = a.fcol + (size_t)c * kFoldStride;
-    const int nr = rl[0], nc = cl[0];
-    T s0 = T(0), s1 = T(0);
-    for (int i = 0; i < nr; ++i) {
-      const int ri = rl[1 + i];
-      const int tr = ri >> 8, er = ri & 255;
-      for (int j = 0; j < nc; ++j) {
-        const int cj = cl[1 + j];
-        const size_t tile = (size_t)tr * a.g.ntc + (cj >> 8);
-        const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & 255);
-        s0 += a.acc[off];
-        if (has1) s1 += a.acc[off + plane];
+  // Each thread holds at most EPT of the nb * W elements (blockDim.x * EPT
+  // >= nb * W, as the LDS FFT needs): unrolled, so the list and data loads of
+  // its elements are in flight together.  The first two entries of each list
+  // are read with its count (the lists are kFoldStride > 2 ints long) and
+  // used only below the count.
+#pragma unroll
+  for (int it = 0; it < EPT; ++it) {
+    const int idx = threadIdx.x + it * blockDim.x;
+    if (idx < nb * W) {
+      const int rr = idx / W, c = idx - rr * W;
+      const int* rl = a.frow + (size_t)(row0 + rr) * kFoldStride;
+      const int* cl = a.fcol + (size_t)c * kFoldStride;
+      const int nr = rl[0], nc = cl[0];
+      const int r0e = rl[1], r1e = rl[2], c0e = cl[1], c1e = cl[2];
+      T s0 = T(0), s1 = T(0);
+      for (int i = 0; i < nr; ++i) {
+        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[1 + i]);
+        const int tr = ri >> 8, er = ri & 255;
+        for (int j = 0; j < nc; ++j) {
+          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[1 + j]);
+          const size_t tile = (size_t)tr * a.g.ntc + (cj >> 8);
+          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & 255);
+          s0 += a.acc[off];
+          if (has1) s1 += a.acc[off + plane];
+        }
       }
+      buf[idx] = C2<T>{s0, s1};
     }
-    buf[idx] = C2<T>{s0, s1};
   }
   __syncthreads();
   fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, false);
@@ -506,9 +516,13 @@ __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __rest
   C2<T>* tw = buf + CB * H;  // twiddles, or Bluestein scratch
   if (!a.plan.blu)
     for (int t = threadIdx.x; t < H; t += blockDim.x) tw[t] = a.tab.tw[t];
-  for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
-    const int y = idx / nb, j = idx - y * nb;
-    buf[idx] = sp[(size_t)y * W + j];
+#pragma unroll
+  for (int it = 0; it < EPT; ++it) {  // blockDim.x * EPT >= H * nb: loads in flight together
+    const int idx = threadIdx.x + it * blockDim.x;
+    if (idx < H * nb) {
+      const int y = idx / nb, j = idx - y * nb;
+      buf[idx] = sp[(size_t)y * W + j];
+    }
   }
   __syncthreads();
   // forward column DFT, division by the symbol, inverse column DFT
@@ -541,7 +555,11 @@ __global__ void __launch_bounds__(MAXT) fft_rows_inv_kernel(const RowInvArgs<T>*
   C2<T>* tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
   if (!a.plan.blu)
     for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tab.tw[t];
-  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) buf[idx] = in[idx];
+#pragma unroll
+  for (int it = 0; it < EPT; ++it) {  // blockDim.x * EPT >= nb * W: loads in flight together
+    const int idx = threadIdx.x + it * blockDim.x;
+    if (idx < nb * W) buf[idx] = in[idx];
+  }
   __syncthreads();
   fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, true);
   const int k0 = 2 * m, k1 = 2 * m + 1;
