@@ -65,13 +65,31 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   double* coef = tot + 6 * 64;
   T* v4buf = reinterpret_cast<T*>(coef + 5 * 64);
 
-  for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
-    const int k = idx / plane;
-    const int rem = idx - k * plane;
-    const int er = rem / EC, ec = rem - er * EC;
-    const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
-    zt[idx] = gz[((size_t)k * H + gr) * W + gc];
-    acc[idx] = T(0);
+  // z over the grown tile, four loads per thread in flight at a time (a
+  // plain strided loop waits for each load before issuing the next)
+  const int ntot = K * plane;
+  for (int i0 = threadIdx.x; i0 < ntot; i0 += 4 * blockDim.x) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * blockDim.x;
+      v[u] = T(0);
+      if (idx < ntot) {
+        const int k = idx / plane;
+        const int rem = idx - k * plane;
+        const int er = rem / EC, ec = rem - er * EC;
+        const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
+        v[u] = gz[((size_t)k * H + gr) * W + gc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * blockDim.x;
+      if (idx < ntot) {
+        zt[idx] = v[u];
+        acc[idx] = T(0);
+      }
+    }
   }
   __syncthreads();
 
