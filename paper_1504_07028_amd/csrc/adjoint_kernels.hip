@@ -55,15 +55,34 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
   double* tot = reinterpret_cast<double*>(part + 2 * NS * nw * 64);
   double* coef = tot + NS * 64;
 
-  for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
-    const int k = idx / plane;
-    const int rem = idx - k * plane;
-    const int er = rem / EC, ec = rem - er * EC;
-    const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
-    const size_t gi = ((size_t)k * H + gr) * W + gc;
-    zt[idx] = a.z[gi];
-    rt[idx] = a.r[gi];
-    acc[idx] = T(0);
+  // z and rb over the grown tile, four elements per thread in flight at a
+  // time (a plain strided loop waits for each load before issuing the next)
+  const int ntot = K * plane;
+  for (int i0 = threadIdx.x; i0 < ntot; i0 += 4 * blockDim.x) {
+    T vz[4], vr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * blockDim.x;
+      vz[u] = vr[u] = T(0);
+      if (idx < ntot) {
+        const int k = idx / plane;
+        const int rem = idx - k * plane;
+        const int er = rem / EC, ec = rem - er * EC;
+        const int gr = wrap_index(r0 - M + er, H), gc = wrap_index(c0 - M + ec, W);
+        const size_t gi = ((size_t)k * H + gr) * W + gc;
+        vz[u] = a.z[gi];
+        vr[u] = a.r[gi];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int idx = i0 + u * blockDim.x;
+      if (idx < ntot) {
+        zt[idx] = vz[u];
+        rt[idx] = vr[u];
+        acc[idx] = T(0);
+      }
+    }
   }
   __syncthreads();
 
