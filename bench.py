@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
 """Throughput of the SegSALSA-STR SALSA loop on one MI355X.
 
-One step = one call of segsalsa_str_solve on the workload: initialisation and
-all rounds (proximity operators, multiplier updates, J^T scatter, FFT z-solve),
-inputs resident in device memory.  The metric is pixel*class*rounds per second.
-The FP32 path is the headline; it counts only if its z is within 2e-4
-(max-abs) of the FP64 path on the same input (the FP64 path is pinned to the
-FP64 CPU oracle by the GPU tests).  Printed as one JSON line.
+Headline workload: the 2048 x 2048, K = 16, 5x5-patch, 500-round solve (the
+largest single-GPU configuration).  One step = one call of segsalsa_str_solve
+on it: initialisation and all 500 rounds (proximity operators, multiplier
+updates, J^T scatter, FFT z-solve), inputs resident in device memory.  The
+metric is pixel*class*rounds per second of the FP32 path; it counts only if
+the FP32 z is within 2e-4 (max-abs) of the FP64 z of the same input after
+the whole solve (the FP64 path is pinned to the FP64 CPU oracle by the GPU
+tests).  The 64-image batch is reported as a second, named entry.  Printed
+as one JSON line.
 """
 from __future__ import annotations
 
@@ -94,23 +97,30 @@ def phase_times(S, torch, call, steps):
             for name in S.PHASES[:4]}
 
 
-def cpu_baseline(wl, probs, weights, budget_s: float):
-    """The FP64 oracle on the same input, timed on this host for a bounded number of rounds."""
+def cpu_baseline(wl, probs, weights, budget_s: float, crop: int = 256):
+    """The FP64 oracle timed on this host on a bounded sample of the workload: the top-left
+    crop x crop pixels of the same input (all K classes, same patch and parameters, periodic
+    boundary on the crop), as many rounds as fit in about budget_s seconds.  The per-unit rate
+    (pixel*class*rounds/s) is what is compared; the oracle's cost per unit does not depend on
+    the image size except through the FFT's log factor."""
     from threadpoolctl import threadpool_limits
     from oracle import segsalsa_ref as R
+    H, W = min(crop, wl.H), min(crop, wl.W)
+    x = np.ascontiguousarray(probs[:, :H, :W])
     pr = R.Problem(np.asarray(weights, dtype=np.float64), wl.M, wl.schatten_p, wl.lam, wl.mu)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        st, ph = R.solve(probs, pr, 1, return_state=True)
+        R.solve(x, pr, 1)
         t1 = time.perf_counter() - t0
         rounds = int(max(1, min(wl.iters, budget_s / max(t1, 1e-6))))
         t0 = time.perf_counter()
-        R.solve(probs, pr, rounds)
+        R.solve(x, pr, rounds)
         dt = time.perf_counter() - t0
-    units = wl.n * wl.K * rounds
+    units = H * W * wl.K * rounds
     return dict(value=units / dt, unit=UNIT, cores=1, kind="oracle",
-                sample=f"{wl.name}: {rounds} of {wl.iters} rounds from the initial state, FP64 numpy, "
-                       f"1 thread (BLAS/FFT limited to 1), {dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
+                sample=f"{wl.name}: its top-left {H}x{W} crop (K = {wl.K}, {2 * wl.M + 1}x{2 * wl.M + 1} patch), "
+                       f"{rounds} rounds from the initial state, FP64 numpy, 1 thread (BLAS/FFT limited to 1), "
+                       f"{dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
 
 
 def bench_adjoint(S, torch, synth, steps, warmup, ck=10):
@@ -229,8 +239,16 @@ def bench_sweep(S, torch, synth, wl_name="pines_145x145_k16", radii=(0, 1, 2, 3,
     return out
 
 
-def bench_batch(S, torch, synth, args):
-    """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one graph launch per step."""
+def plan_record(S, K, H, W, M, prec):
+    t, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+    rec = {k: v for k, v in t.items() if k != "us_per_round"}
+    rec["tuned"] = tuned
+    return rec
+
+
+def bench_batch(S, torch, synth, steps, warmup, fp32_only=False, graph=True):
+    """The 64-image batch (sides 96..512, K in {4, 8, 9, 16}, 3x3 patch, 200 rounds): one step is
+    one segsalsa_str_solve_batch call (one graph launch)."""
     B = synth.BATCH
     shapes = synth.batch_shapes()
     probs = [t[0] for t in synth.make_batch(shapes)]
@@ -241,54 +259,68 @@ def bench_batch(S, torch, synth, args):
     L = (2 * B["M"] + 1) ** 2
     out, zs = {}, {}
     for dtype, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
-        if args.fp32_only and tag == "f64":
+        if fp32_only and tag == "f64":
             continue
         packed = torch.cat([torch.from_numpy(x).reshape(-1) for x in probs]).to(device="cuda", dtype=dtype)
         z = torch.empty_like(packed)
-        params = S.BatchParams(B["M"], c, 1.0, B["iters"], use_graph=not args.no_graph)
+        params = S.BatchParams(B["M"], c, 1.0, B["iters"], use_graph=graph)
         ws = torch.empty(S.segsalsa_str_batch_workspace_size(imgs, params, S._prec(dtype)), dtype=torch.uint8,
                          device="cuda")
         log(f"[bench] batch {tag}")
-        ms, _ = time_calls(torch, lambda: S.segsalsa_str_solve_batch(imgs, params, packed, z, ws), args.steps,
-                           args.warmup)
+        n_steps, n_warm = (steps, warmup) if tag == "f32" else (max(1, min(2, steps)), 1)
+        ms, _ = time_calls(torch, lambda: S.segsalsa_str_solve_batch(imgs, params, packed, z, ws), n_steps, n_warm)
         direct = S.BatchParams(B["M"], c, 1.0, B["iters"])
-        ph = phase_times(S, torch, lambda: S.segsalsa_str_solve_batch(imgs, direct, packed, z, ws), args.steps)
+        ph = phase_times(S, torch, lambda: S.segsalsa_str_solve_batch(imgs, direct, packed, z, ws), 1)
         zs[tag] = z.double()
         out[tag] = dict(ms_per_step=ms, value=units / (ms * 1e-3), phases=ph)
         log(f"[bench] batch {tag}: {ms:.2f} ms/step {units / (ms * 1e-3):.4g} units/s {ph}")
         del ws, packed
         torch.cuda.empty_cache()
     z_err = float(torch.max(torch.abs(zs["f32"] - zs["f64"])).item()) if "f64" in zs else None
-    prox = out["f32"]["phases"]["prox_rhs"]
-    bytes_launch = sum(H * W * K for (H, W, K) in shapes) * prox_bytes_per_unit(L, 4)
+    n_units = sum(H * W * K for (H, W, K) in shapes)
+    prox = out["f32"]["phases"]["prox_rhs"]   # all prox launches of a round (one per workgroup shape)
+    bytes_launch = n_units * prox_bytes_per_unit(L, 4)
     achieved = bytes_launch / (prox["avg_us"] * 1e-6) / 1e9
-    res = {"metric": METRIC, "value": out["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0,
-           "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": out["f32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": B["name"], "images": len(shapes), "pixels": sum(H * W for H, W, _ in shapes),
-                      "patch": "3x3", "rounds": B["iters"]},
-           "roofline": {"bound": "hbm", "kernel": "prox_rhs (all groups)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+    round_us = out["f32"]["ms_per_step"] * 1e3 / B["iters"]
+    res = {"workload": B["name"], "value": out["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0,
+           "unit": UNIT, "ms_per_step": out["f32"]["ms_per_step"], "steps": steps, "warmup": warmup, "dtype": "f32",
+           "config": {"images": len(shapes), "pixels": sum(H * W for H, W, _ in shapes), "units_per_round": n_units,
+                      "patch": "3x3", "rounds": B["iters"], "graph": graph},
+           "roofline": {"bound": "hbm", "kernel": "prox_rhs (all launches of a round)", "achieved": achieved,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                         "bytes_per_launch_alg": bytes_launch, "avg_launch_us": prox["avg_us"]},
+           "round_roofline": round_roofline(n_units, L, round_us),
            "z_err_fp32_vs_fp64": z_err,
-           "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in out["f32"]["phases"].items()}}
+           "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in out["f32"]["phases"].items()},
+           "plans": [dict(K=K, H=H, W=W, **plan_record(S, K, H, W, B["M"], S.SEGSALSA_FP32)) for (H, W, K) in shapes]}
     if "f64" in out:
         res["fp64"] = {"value": out["f64"]["value"], "ms_per_step": out["f64"]["ms_per_step"]}
         res["speedup_fp32_vs_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
     return res
 
 
+def round_roofline(n_units, L, round_us, b=4):
+    """Whole round (prox + the three FFT passes) against HBM: (4L + 15) words per pixel*class,
+    the prox kernel's (4L + 9) plus the FFT passes' right-hand side and two spectrum round trips."""
+    achieved = n_units * (4 * L + 15) * b / (round_us * 1e-6) / 1e9
+    return {"bound": "hbm", "bytes_per_unit": (4 * L + 15) * b, "us_per_round": round_us, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pines_145x145_k16")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large_2048x2048_k16")
+    ap.add_argument("--rounds", type=int, default=None,
+                    help="override the workload's round count (profiler runs; the line then is not the headline)")
     ap.add_argument("--schatten-p", type=float, default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-solve measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-image batch entry")
+    ap.add_argument("--no-variants", action="store_true", help="skip the simplex-g4 / general-p measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="patch-size sweep 1x1 ... 11x11 on the workload (accuracy vs the synthetic ground truth)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -330,13 +362,16 @@ def main():
         return
 
     if args.workload == synth.BATCH["name"]:
-        print(json.dumps(bench_batch(S, torch, synth, args)), flush=True)
+        print(json.dumps(bench_batch(S, torch, synth, args.steps, args.warmup, args.fp32_only, not args.no_graph)),
+              flush=True)
         return
 
+    import dataclasses
     wl = synth.WORKLOADS[args.workload]
     if args.schatten_p is not None:
-        import dataclasses
         wl = dataclasses.replace(wl, schatten_p=args.schatten_p)
+    if args.rounds is not None:
+        wl = dataclasses.replace(wl, iters=args.rounds)
     d = synth.make_workload(wl)
     units = wl.n * wl.K * wl.iters
     res = {}
@@ -349,13 +384,19 @@ def main():
                        use_graph=not args.no_graph)
         ws = torch.empty(S.segsalsa_str_workspace_size(pr, S._prec(dtype)), dtype=torch.uint8, device="cuda")
         z = torch.empty_like(x)
-        log(f"[bench] {wl.name} {tag}: warmup {args.warmup}, steps {args.steps}, graph {not args.no_graph}")
-        ms_gpu, ms_wall = time_calls(torch, lambda: S.segsalsa_str_solve(pr, x, z, ws), args.steps, args.warmup)
+        # FP64 is timed over at most two solves (no warm-up: it is the reference for the error gate)
+        n_steps, n_warm = (args.steps, args.warmup) if tag == "f32" else (max(1, min(2, args.steps)), 0)
+        log(f"[bench] {wl.name} {tag}: warmup {n_warm}, steps {n_steps}, graph {not args.no_graph}")
+        ms_gpu, ms_wall = time_calls(torch, lambda: S.segsalsa_str_solve(pr, x, z, ws), n_steps, n_warm)
         zs[tag] = z.double().cpu().numpy()
-        # per-kernel durations: a second pass over the same steps, direct launches with HIP events around each
-        pr_direct = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters)
-        phases = phase_times(S, torch, lambda: S.segsalsa_str_solve(pr_direct, x, z, ws), args.steps)
-        res[tag] = dict(ms_per_step=ms_gpu, ms_wall=ms_wall, value=units / (ms_gpu * 1e-3), phases=phases)
+        phases = None
+        if tag == "f32":
+            # per-kernel durations: one more solve, direct launches with HIP events around each
+            # launch, recorded on the solve's stream
+            pr_direct = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters)
+            phases = phase_times(S, torch, lambda: S.segsalsa_str_solve(pr_direct, x, z, ws), 1)
+        res[tag] = dict(ms_per_step=ms_gpu, ms_wall=ms_wall, value=units / (ms_gpu * 1e-3), phases=phases,
+                        plan=plan_record(S, wl.K, wl.H, wl.W, wl.M, S._prec(dtype)))
         log(f"[bench] {tag}: {ms_gpu:.3f} ms/step, {units / (ms_gpu * 1e-3):.4g} units/s, phases {phases}")
         del ws, x, z
         torch.cuda.empty_cache()
@@ -368,6 +409,7 @@ def main():
     src_hash = kernel_source_hash()
     traffic = load_traffic(wl.name, "f32", src_hash)
     value = res["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0
+    round_us = res["f32"]["ms_per_step"] * 1e3 / max(1, wl.iters)
     out = {
         "metric": METRIC,
         "value": value,
@@ -382,22 +424,26 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "H": wl.H, "W": wl.W, "K": wl.K, "patch": f"{2 * wl.M + 1}x{2 * wl.M + 1}",
-                   "schatten_p": wl.schatten_p, "lambda": wl.lam, "mu": wl.mu, "rounds": wl.iters},
+                   "schatten_p": wl.schatten_p, "lambda": wl.lam, "mu": wl.mu, "rounds": wl.iters,
+                   "graph": not args.no_graph, "plan": res["f32"]["plan"]},
         "roofline": {"bound": "hbm", "kernel": "prox_rhs", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch_alg": bytes_launch,
                      "avg_launch_us": prox["avg_us"], "kernel_source_hash": src_hash},
+        "round_roofline": round_roofline(wl.n * wl.K, wl.L, round_us),
         "z_err_fp32_vs_fp64": z_err,
         "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in res["f32"]["phases"].items()},
     }
     if "f64" in res:
         out["fp64"] = {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
-                       "phases_us": {k: round(v["avg_us"], 3) for k, v in res["f64"]["phases"].items()}}
+                       "plan": res["f64"]["plan"]}
         out["speedup_fp32_vs_fp64"] = res["f64"]["ms_per_step"] / res["f32"]["ms_per_step"]
+    if not args.no_batch:
+        out["batch"] = bench_batch(S, torch, synth, args.steps, args.warmup, args.fp32_only, not args.no_graph)
     if not args.no_adjoint and not args.fp32_only:
-        out["adjoint"] = bench_adjoint(S, torch, synth, max(2, args.steps // 2), 1)
-    if not args.fp32_only:
-        out["variants"] = bench_variants(S, torch, synth, max(2, args.steps // 3), 1)
+        out["adjoint"] = bench_adjoint(S, torch, synth, 2, 1)
+    if not args.fp32_only and not args.no_variants:
+        out["variants"] = bench_variants(S, torch, synth, 2, 1)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, d["probs"], d["weights"], args.cpu_seconds)

@@ -262,6 +262,69 @@ segsalsa_status segsalsa_str_backward(const segsalsa_problem *prob, segsalsa_pre
                                       size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Launch shapes (not part of the method).  The planner picks, per image
+ * shape (K, H, W, patch_radius, precision), the prox kernel's tile and
+ * classes per wavefront and the blocking of the FFT passes from a cost
+ * model.  A process-wide tuning table, filled by segsalsa_str_autotune
+ * (measured on the device) or by the caller, overrides those choices for the
+ * shapes it holds; forward solves and batches of such images then use the
+ * tuned shapes (the differentiable solve keeps the planner's).  A tuned entry
+ * changes the launch shapes and the workspace size, not the arithmetic: the
+ * results agree with untuned ones to rounding (the fold and the class sums
+ * are added in another order).  Size workspaces after changing the table.
+ * All functions are thread-safe.
+ */
+typedef struct {
+  int32_t tile_rows, tile_cols;  /* prox tile in pixels (both > 0), or 0 for the planner's            */
+  int32_t classes_per_wave;      /* classes per wavefront of the prox kernel: 1, 2 or 4, or 0          */
+  int32_t rows_per_block;        /* rows per workgroup of the row DFT passes (> 0), or 0               */
+  int32_t row_threads;           /* threads per row workgroup, a multiple of 64 in [64, 1024], or 0    */
+  int32_t cols_per_block;        /* columns per workgroup of the column pass (> 0), or 0               */
+  int32_t col_threads;           /* threads per column workgroup, as row_threads, or 0                 */
+  double us_per_round;           /* measured microseconds per round with this entry (0 = not measured) */
+} segsalsa_tuning;
+
+/* Set (or, with tuning == NULL, remove) the entry of one shape.  The entry is
+ * checked against the planner's limits (LDS, registers, fold lists) and
+ * refused with INVALID_ARG / UNSUPPORTED if it does not fit. */
+segsalsa_status segsalsa_tuning_set(int32_t K, int32_t H, int32_t W, int32_t patch_radius,
+                                    segsalsa_precision precision, const segsalsa_tuning *tuning /* HOST */);
+/* The shapes the planner uses for this image shape (every field filled in) and
+ * whether they come from the table (*tuned = 1) or the cost model (0). */
+segsalsa_status segsalsa_tuning_get(int32_t K, int32_t H, int32_t W, int32_t patch_radius,
+                                    segsalsa_precision precision, segsalsa_tuning *out /* HOST */,
+                                    int32_t *tuned /* HOST, may be NULL */);
+/* Remove every entry. */
+segsalsa_status segsalsa_tuning_clear(void);
+/* Read entries from a JSON tuning cache written by segsalsa_tuning_save and
+ * add them to the table (entries that do not fit are skipped and counted in
+ * *skipped, which may be NULL).  A missing or unreadable file is INVALID_ARG. */
+segsalsa_status segsalsa_tuning_load(const char *path, int32_t *loaded /* HOST, may be NULL */,
+                                     int32_t *skipped /* HOST, may be NULL */);
+/* Write the whole table as a JSON tuning cache. */
+segsalsa_status segsalsa_tuning_save(const char *path);
+
+/*
+ * Measure launch shapes for `prob`'s image shape on the device and store the
+ * fastest in the tuning table (and in *best if given).  Coordinate search:
+ * prox tile and classes per wavefront by the time of whole rounds, then the
+ * row DFT blocking by the time of the two row passes, then the column
+ * blocking by the time of the column pass; each candidate runs the
+ * initialisation from `input` and 1 + rounds rounds (rounds in [1, 100]) and
+ * is timed with HIP events on `stream`.  Waits for `stream`.  z_scratch is a
+ * [K][H][W] array of the precision's type that receives z (overwritten).
+ * The workspace must hold segsalsa_str_autotune_workspace_size bytes (the
+ * largest candidate's).  Only prob's shape, patch radius, weights, p,
+ * lambda and mu are used (a fixed-round forward solve).
+ */
+segsalsa_status segsalsa_str_autotune_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
+                                                     size_t *bytes /* HOST, out */);
+segsalsa_status segsalsa_str_autotune(const segsalsa_problem *prob, segsalsa_precision precision,
+                                      const void *input, void *z_scratch, void *workspace, size_t workspace_bytes,
+                                      int32_t rounds, segsalsa_tuning *best /* HOST, may be NULL */,
+                                      hipStream_t stream);
+
+/*
  * Instrumentation (not part of the method): per-phase GPU time of the rounds
  * enqueued by segsalsa_str_solve, measured with HIP events recorded on the
  * caller's stream immediately before and after each kernel launch.  Off by

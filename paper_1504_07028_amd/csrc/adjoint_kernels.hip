@@ -35,7 +35,7 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
   constexpr int L = D * D;
   constexpr int NS = 10;  // cross-class sums per pixel
   const TileGeom& g = a.g;
-  const int tile = blockIdx.x;
+  const int tile = xcd_block();   // neighbouring tiles (shared halo rows) on one XCD
   const int tr = tile / g.ntc;
   const int tc = tile - tr * g.ntc;
   const int r0 = g.r0(tr), c0 = g.c0(tc);
@@ -349,16 +349,16 @@ __global__ void __launch_bounds__(256) adj_input_kernel(const AdjIOArgs<T> a) {
   tile_pos(a.g, r, c, tile, step, lane);
   const size_t sb = ((size_t)tile * a.g.steps + step) * K;
   const size_t plane = (size_t)a.g.ER * a.g.EC;
-  const int* rl = a.frow + (size_t)r * kFoldStride;
-  const int* cl = a.fcol + (size_t)c * kFoldStride;
+  const int* rl = a.frow + r;   // [kFoldStride][H]: count, then the entries
+  const int* cl = a.fcol + c;
   auto folded = [&](int k) {
     T s = T(0);
     for (int u = 0; u < rl[0]; ++u) {
-      const int ri = rl[1 + u];
+      const int ri = rl[(size_t)(1 + u) * H];
       for (int v = 0; v < cl[0]; ++v) {
-        const int ci = cl[1 + v];
-        const size_t t = (size_t)(ri >> 8) * a.g.ntc + (ci >> 8);
-        s += a.acc[(t * K + k) * plane + (size_t)(ri & 255) * a.g.EC + (ci & 255)];
+        const int ci = cl[(size_t)(1 + v) * W];
+        const size_t t = (size_t)(ri >> kFoldShift) * a.g.ntc + (ci >> kFoldShift);
+        s += a.acc[(t * K + k) * plane + (size_t)(ri & kFoldMask) * a.g.EC + (ci & kFoldMask)];
       }
     }
     return (double)s + (double)a.pbar[(sb + k) * 64 + lane];

@@ -9,8 +9,10 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "segsalsa_internal.h"
@@ -103,12 +105,12 @@ struct Plan {
   int g4s;        // simplex g4: the prox kernel stages v4 of all classes in LDS
   size_t adj_lds;
   FftPlanDev frow, fcol;
+  // FFT workgroups: transforms per workgroup, threads, elements per thread
   int rows_per_block, row_threads, row_ept;
-  int row_threads_n, row_ept_n;  // FP64 narrow sizing (at most kFftNarrowThreads threads), 0 if it does not fit
   size_t row_lds;
   int cols_per_block, col_threads, col_ept;
-  int col_threads_n, col_ept_n;
   size_t col_lds;
+  bool tuned;     // the prox tile, classes per wavefront and FFT blocking came from the tuning table
   // workspace offsets (bytes)
   size_t off_flags, off_twW, off_twH, off_sx, off_sy, off_frow, off_fcol, off_phat, off_dm, off_d2, off_acc, off_spec,
       off_zprev, off_restile, off_partial, off_out, off_chW, off_chH, off_bfW, off_bfH, off_twMW, off_twMH, total;
@@ -134,83 +136,120 @@ TileGeom tile_geom(const Plan& p, int tr, int tc) {
 
 bool fold_lists_fit(const TileGeom& g) {
   for (int r = 0; r < g.H; ++r)
-    if (fold_list(g, r, true, nullptr) < 0) return false;
+    if (fold_list(g, r, true, nullptr, 0) < 0) return false;
   for (int c = 0; c < g.W; ++c)
-    if (fold_list(g, c, false, nullptr) < 0) return false;
+    if (fold_list(g, c, false, nullptr, 0) < 0) return false;
   return true;
 }
 
-// Tile grid of the prox kernel.  A workgroup processes one tile in
-// ceil(pixels / 64) steps plus a fixed load/store phase; tiles run in
-// batches of (compute units x resident workgroups).  Among the shapes whose
-// LDS footprint fits, take the one with the fewest batches x (steps + 1),
-// breaking ties by the smaller grown-tile overhead.  SEGSALSA_TILE=RxC forces
-// a shape (tuning runs).
-bool choose_tiles(Plan& p) {
-  static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
-  static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64};
+// LDS bytes of the prox workgroup (and of the reverse sweep's, for
+// differentiable solves) on the grown tile of g.
+size_t prox_lds_fwd(const Plan& p, const TileGeom& g) {
   // partial sums [2][6][nw][64] (T), per-pixel FP64 sums [6][64] and coefficients [5][64], v4 stage (simplex g4)
   const size_t part = 12 * (size_t)p.nw * 64 + (p.g4s ? 2 * (size_t)p.K * 64 : 0);
-  auto fwd_lds = [&](const TileGeom& g) {
-    return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 11 * 64 * 8 + 16;
-  };
+  return (2 * (size_t)p.K * g.ER * g.EC + part) * p.ts + 11 * 64 * 8 + 16;
+}
+size_t prox_lds_adj(const Plan& p, const TileGeom& g) {
   // reverse sweep: z, the solved cotangent and the accumulator over the grown tile
-  auto adj_lds = [&](const TileGeom& g) {
-    return p.anw ? (3 * (size_t)p.K * g.ER * g.EC + 20 * (size_t)p.anw * 64) * p.ts + 20 * 64 * 8 + 16 : 0;
-  };
-  auto lds_of = [&](const TileGeom& g) { return std::max(fwd_lds(g), adj_lds(g)); };
+  return p.anw ? (3 * (size_t)p.K * g.ER * g.EC + 20 * (size_t)p.anw * 64) * p.ts + 20 * 64 * 8 + 16 : 0;
+}
+
+// Tile shapes that fit LDS, best first by the cost model: a workgroup
+// processes one tile in ceil(pixels / 64) steps plus a fixed load/store
+// phase and tiles run in batches of (compute units x resident workgroups),
+// so the cost is batches x (steps + 1); ties go to the smaller grown-tile
+// overhead.
+std::vector<TileGeom> tile_candidates(const Plan& p) {
+  static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
+  static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
   // resident workgroups per CU allowed by the register budget of the chosen instantiation
   const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw) / 256);
   const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
-  const char* env = std::getenv("SEGSALSA_TILE");
-  int fr = 0, fc = 0;
-  if (env && std::sscanf(env, "%dx%d", &fr, &fc) == 2 && fr > 0 && fc > 0) {
-    TileGeom g = tile_geom(p, fr, fc);
-    if (lds_of(g) <= kLdsBudget && fold_lists_fit(g)) {
-      p.g = g;
-      p.prox_lds = fwd_lds(g);
-      p.adj_lds = adj_lds(g);
-      return true;
-    }
-  }
-  bool have = false;
-  TileGeom best{};
-  double best_cost = 0, best_over = 0;
+  struct Cand {
+    TileGeom g;
+    double cost, over;
+  };
+  std::vector<Cand> cs;
   for (int tr : rows) {
     for (int tc : cols) {
       TileGeom g = tile_geom(p, tr, tc);
-      const size_t lds = lds_of(g);
+      bool dup = false;
+      for (const Cand& c : cs) dup |= c.g.ntr == g.ntr && c.g.ntc == g.ntc;
+      if (dup) continue;
+      const size_t lds = std::max(prox_lds_fwd(p, g), prox_lds_adj(p, g));
       if (lds > kLdsBudget) continue;
       const int occ = std::max(1, std::min(occ_regs, (int)(kLdsBudget / lds)));
       const long long slots = (long long)kTargetGroups * occ;
       const long long batches = (g.ntiles() + slots - 1) / slots;
-      const double cost = (double)batches * (g.steps + 1);
-      const double over = (double)g.ER * g.EC / ((double)g.TR * g.TC);
-      if (!have || cost < best_cost || (cost == best_cost && over < best_over)) {
-        if (!fold_lists_fit(g)) continue;
-        have = true;
-        best = g;
-        best_cost = cost;
-        best_over = over;
-      }
+      cs.push_back({g, (double)batches * (g.steps + 1), (double)g.ER * g.EC / ((double)g.TR * g.TC)});
     }
   }
-  if (!have) return false;
-  p.g = best;
-  p.prox_lds = fwd_lds(best);
-  p.adj_lds = adj_lds(best);
-  return true;
+  std::stable_sort(cs.begin(), cs.end(), [](const Cand& a, const Cand& b) {
+    return a.cost != b.cost ? a.cost < b.cost : a.over < b.over;
+  });
+  std::vector<TileGeom> out;
+  for (const Cand& c : cs) out.push_back(c.g);
+  return out;
 }
 
-// Elements per thread (2, 4, 8 or 16) and workgroup size of an LDS FFT
-// workgroup holding `items` complex elements: the fewest elements per thread
-// that keep the workgroup within 1024 threads.
-void fft_threads(long long items, int max_threads, int& ept, int& threads) {
-  ept = 2;
-  while (ept < kFftEptMax && (items + ept - 1) / ept > max_threads) ept *= 2;
-  long long t = (items + ept - 1) / ept;
+// Tile grid of the prox kernel: force_r x force_c (a tuned shape) if it fits,
+// else the best candidate whose fold lists fit.
+bool choose_tiles(Plan& p, int force_r, int force_c) {
+  auto take = [&](const TileGeom& g) {
+    p.g = g;
+    p.prox_lds = prox_lds_fwd(p, g);
+    p.adj_lds = prox_lds_adj(p, g);
+  };
+  if (force_r > 0 && force_c > 0) {
+    TileGeom g = tile_geom(p, force_r, force_c);
+    if (std::max(prox_lds_fwd(p, g), prox_lds_adj(p, g)) > kLdsBudget || !fold_lists_fit(g)) return false;
+    take(g);
+    return true;
+  }
+  for (const TileGeom& g : tile_candidates(p)) {
+    if (!fold_lists_fit(g)) continue;
+    take(g);
+    return true;
+  }
+  return false;
+}
+
+// Elements per thread of an LDS FFT workgroup of `threads` threads holding
+// `items` complex elements: the fewest of 2, 4, 8, 16 with threads * ept >=
+// items, or 0 if even 16 do not suffice.
+int fft_ept(long long items, int threads) {
+  for (int e = 2; e <= kFftEptMax; e *= 2)
+    if ((long long)threads * e >= items) return e;
+  return 0;
+}
+
+// Threads for `items` elements at about `per` elements per thread (a
+// multiple of 64, at most 1024).
+int fft_threads_for(long long items, int per) {
+  long long t = (items + per - 1) / per;
   t = (t + 63) / 64 * 64;
-  threads = (int)std::max<long long>(64, std::min<long long>(t, max_threads));
+  return (int)std::max<long long>(64, std::min<long long>(t, kFftMaxThreads));
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table: launch shapes for images of one (K, H, W, M, precision),
+// measured by segsalsa_str_autotune or set by the caller, read by the planner.
+// ---------------------------------------------------------------------------
+struct TuneKey {
+  int K, H, W, M, fp64;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(K, H, W, M, fp64) < std::tie(o.K, o.H, o.W, o.M, o.fp64);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, segsalsa_tuning> g_tune;
+
+bool tuning_lookup(int K, int H, int W, int M, bool fp64, segsalsa_tuning& out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(TuneKey{K, H, W, M, fp64 ? 1 : 0});
+  if (it == g_tune.end()) return false;
+  out = it->second;
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,19 +329,19 @@ segsalsa_status validate_problem(const segsalsa_problem* pr, segsalsa_precision 
 // Per-image plan: tile grid, FFT factorisations and launch shapes, and the
 // layout of the image's region of the workspace (offsets from its base).
 // ---------------------------------------------------------------------------
-segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
+segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_tuning& tn, Plan& p) {
   p.fp64 = c.fp64;
   p.ts = c.ts;
   p.K = K; p.H = H; p.W = W; p.M = c.M;
   p.L = c.L;
   p.P = (K + 1) / 2;
   p.g4s = c.g4s;
-  // prox workgroup: fewest classes per wavefront whose register budget allows ceil(K/kpw) wavefronts
+  p.tuned = false;
+  // prox workgroup: the tuned classes per wavefront, else the fewest whose
+  // register budget allows ceil(K/kpw) wavefronts
   p.kpw = 0;
-  int kpw_first = 1;
-  if (const char* ek = std::getenv("SEGSALSA_KPW")) kpw_first = std::atoi(ek);
   for (int kpw : {1, 2, 4}) {
-    if (kpw < kpw_first) continue;
+    if (tn.classes_per_wave > 0 && kpw != tn.classes_per_wave) continue;
     const int nw = ceil_div(K, kpw);
     if (nw <= 16 && nw * 64 <= prox_max_threads_rt(p.fp64, p.M, kpw)) {
       p.kpw = kpw;
@@ -311,6 +350,9 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
     }
   }
   if (p.kpw == 0) {
+    if (tn.classes_per_wave > 0)
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d: %d classes per wavefront do not fit one workgroup", K,
+                  p.M, tn.classes_per_wave);
     p.kpw = 4;
     p.nw = ceil_div(K, 4);
     if (p.nw * 64 > prox_max_threads_rt(p.fp64, p.M, 4))
@@ -334,51 +376,88 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
         return fail(SEGSALSA_ERR_UNSUPPORTED, "K = %d, M = %d do not fit one adjoint workgroup", K, p.M);
     }
   }
-  if (!choose_tiles(p)) return fail(SEGSALSA_ERR_UNSUPPORTED, "no tile shape fits LDS for K = %d, M = %d", K, p.M);
+  if (!choose_tiles(p, tn.tile_rows, tn.tile_cols)) {
+    if (tn.tile_rows > 0)
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "tile %dx%d does not fit LDS or the fold lists for K = %d, M = %d",
+                  tn.tile_rows, tn.tile_cols, K, p.M);
+    return fail(SEGSALSA_ERR_UNSUPPORTED, "no tile shape fits LDS for K = %d, M = %d", K, p.M);
+  }
   const size_t cs = 2 * p.ts;
   p.frow = make_fft_plan(W);
   p.fcol = make_fft_plan(H);
-  // FFT workgroups: a few hundred elements per workgroup at one or two per
-  // thread for latency hiding, whole rows (columns) plus the twiddle table in
-  // LDS; column blocks of 8+ columns on tall images for coalesced rows.
-  const long long cap = p.fp64 ? 6144 : 12288;   // complex elements per FFT workgroup
   // Bluestein needs scratch next to the data; where that exceeds LDS, keep
   // the direct stages
   if (p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
   if (p.fcol.blu && ((size_t)H + p.fcol.M) * cs > kLdsBudget) p.fcol.blu = 0;
+  // FFT workgroups.  Rows: whole rows plus the twiddle table (or the
+  // Bluestein scratch) in LDS, about 2048 (FP32) / 1024 (FP64) elements per
+  // workgroup at about 8 per thread (a radix-8 stage then keeps every thread
+  // busy), but no fewer than two workgroups per compute unit when the image
+  // has the rows.  Columns: blocks of adjacent columns so that each row of
+  // a block is one contiguous run, at most 80 KB of LDS (two workgroups per
+  // compute unit) and at least one workgroup per compute unit.
   {
     const int Lr = p.frow.blu ? p.frow.M : W;      // elements per row inside the transform
-    long long rpb = std::max<long long>(1, 512 / Lr);   // about 512 elements per workgroup
-    if (const char* er = std::getenv("SEGSALSA_ROWS_PER_BLOCK")) rpb = std::max(1, std::atoi(er));  // tuning runs
-    rpb = std::max<long long>(1, std::min<long long>(rpb, H));
-    // one workgroup holds at most kFftEptMax elements per thread of kFftMaxThreads, and its LDS
-    while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads ||
-                       ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs > kLdsBudget))
-      --rpb;
+    auto lds_of = [&](long long rpb) {
+      return ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
+    };
+    const long long nrows = (long long)p.P * H;
+    long long rpb;
+    if (tn.rows_per_block > 0) {
+      rpb = std::min<long long>(tn.rows_per_block, H);
+    } else {
+      rpb = std::max<long long>(1, (p.fp64 ? 1024 : 2048) / Lr);
+      rpb = std::min<long long>(rpb, std::max<long long>(1, nrows / (2 * kTargetGroups)));
+      rpb = std::max<long long>(1, std::min<long long>(rpb, H));
+      while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads || lds_of(rpb) > kLdsBudget)) --rpb;
+    }
+    if (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads || lds_of(rpb) > kLdsBudget)
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld rows of %d per FFT workgroup do not fit", rpb, W);
+    const long long items = rpb * Lr;
+    int thr = tn.row_threads > 0 ? tn.row_threads : fft_threads_for(items, 8);
+    int ept = fft_ept(items, thr);
+    if (ept == 0) {
+      if (tn.row_threads > 0)
+        return fail(SEGSALSA_ERR_UNSUPPORTED, "%d row threads hold at most 16 of %lld elements each", thr, items);
+      thr = fft_threads_for(items, kFftEptMax);
+      ept = fft_ept(items, thr);
+    }
     p.rows_per_block = (int)rpb;
-    fft_threads(rpb * Lr, kFftMaxThreads, p.row_ept, p.row_threads);
-    p.row_ept_n = p.row_threads_n = 0;
-    if (p.fp64 && rpb * Lr <= (long long)kFftEptMax * kFftNarrowThreads)
-      fft_threads(rpb * Lr, kFftNarrowThreads, p.row_ept_n, p.row_threads_n);
-    p.row_lds = ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
+    p.row_threads = thr;
+    p.row_ept = ept;
+    p.row_lds = lds_of(rpb);
   }
   {
     const int Lc = p.fcol.blu ? p.fcol.M : H;
-    int cb = 1;
-    while (cb < 64 && cb * 2 <= W && (long long)(cb * 2) * Lc <= cap &&
-           ((long long)(cb * 2) * Lc <= 1024 || cb * 2 <= 8))
-      cb *= 2;
-    if (const char* ec = std::getenv("SEGSALSA_COLS_PER_BLOCK"))  // tuning runs
-      cb = std::max(1, std::min(std::atoi(ec), W));
-    while (cb > 1 && ((long long)cb * Lc > (long long)kFftEptMax * kFftMaxThreads ||
-                      ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs > kLdsBudget))
-      --cb;
-    p.cols_per_block = cb;
-    fft_threads((long long)cb * Lc, kFftMaxThreads, p.col_ept, p.col_threads);
-    p.col_ept_n = p.col_threads_n = 0;
-    if (p.fp64 && (long long)cb * Lc <= (long long)kFftEptMax * kFftNarrowThreads)
-      fft_threads((long long)cb * Lc, kFftNarrowThreads, p.col_ept_n, p.col_threads_n);
-    p.col_lds = ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
+    auto lds_of = [&](long long cb) {
+      return ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
+    };
+    long long cb;
+    if (tn.cols_per_block > 0) {
+      cb = std::min<long long>(tn.cols_per_block, W);
+    } else {
+      cb = 1;
+      const long long cmax = p.fp64 ? 8 : 16;   // 128-byte runs
+      while (cb * 2 <= cmax && cb * 2 <= W && lds_of(cb * 2) <= 80 * 1024 &&
+             cb * 2 * Lc <= (long long)kFftEptMax * kFftMaxThreads &&
+             (long long)p.P * ceil_div(W, (int)(cb * 2)) >= kTargetGroups)
+        cb *= 2;
+    }
+    if (cb * Lc > (long long)kFftEptMax * kFftMaxThreads || lds_of(cb) > kLdsBudget)
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld columns of %d per FFT workgroup do not fit", cb, H);
+    const long long items = cb * Lc;
+    int thr = tn.col_threads > 0 ? tn.col_threads : fft_threads_for(items, 8);
+    int ept = fft_ept(items, thr);
+    if (ept == 0) {
+      if (tn.col_threads > 0)
+        return fail(SEGSALSA_ERR_UNSUPPORTED, "%d column threads hold at most 16 of %lld elements each", thr, items);
+      thr = fft_threads_for(items, kFftEptMax);
+      ept = fft_ept(items, thr);
+    }
+    p.cols_per_block = (int)cb;
+    p.col_threads = thr;
+    p.col_ept = ept;
+    p.col_lds = lds_of(cb);
   }
   const size_t nt = (size_t)p.g.ntiles();
   size_t off = 0;
@@ -408,17 +487,41 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
   p.off_twMW = off; off = align_up(off + (size_t)p.frow.M * cs);
   p.off_twMH = off; off = align_up(off + (size_t)p.fcol.M * cs);
   p.total = off;
+  return SEGSALSA_OK;
+}
+
+// Per-image plan: the tuned entry of the shape if there is one and it fits
+// this problem (forward solves only: the differentiable solve sizes its tiles
+// for the reverse sweep too, and the simplex g4 needs more LDS), else the
+// planner's own choices.
+void log_plan(const Plan& p) {
+  const int K = p.K, H = p.H, W = p.W;
   if (const char* lg = std::getenv("SEGSALSA_LOG")) {
     if (lg[0] == '1')
       std::fprintf(stderr,
-                   "[segsalsa] plan %s K=%d H=%d W=%d M=%d: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
-                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d (narrow %d x %d); cols/block=%d threads=%d "
-                   "ept=%d (narrow %d x %d); region %zu B\n",
-                   p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.g.ntr, p.g.ntc, p.g.TR, p.g.TC, p.g.ntiles(), p.g.steps,
-                   p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads, p.row_ept, p.row_threads_n, p.row_ept_n,
-                   p.cols_per_block, p.col_threads, p.col_ept, p.col_threads_n, p.col_ept_n, p.total);
+                   "[segsalsa] plan %s K=%d H=%d W=%d M=%d%s: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
+                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d lds=%zu; cols/block=%d threads=%d ept=%d "
+                   "lds=%zu; region %zu B\n",
+                   p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.tuned ? " (tuned)" : "", p.g.ntr, p.g.ntc, p.g.TR,
+                   p.g.TC, p.g.ntiles(), p.g.steps, p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads,
+                   p.row_ept, p.row_lds, p.cols_per_block, p.col_threads, p.col_ept, p.col_lds, p.total);
   }
-  return SEGSALSA_OK;
+}
+
+segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
+  segsalsa_tuning tn{};
+  if (!c.grad && tuning_lookup(K, H, W, c.M, c.fp64, tn)) {
+    const std::string saved = g_last_error;
+    if (plan_with(K, H, W, c, tn, p) == SEGSALSA_OK) {
+      p.tuned = true;
+      log_plan(p);
+      return SEGSALSA_OK;
+    }
+    g_last_error = saved;
+  }
+  segsalsa_status s = plan_with(K, H, W, c, segsalsa_tuning{}, p);
+  if (s == SEGSALSA_OK) log_plan(p);
+  return s;
 }
 
 template <typename T>
@@ -493,7 +596,7 @@ struct ImgRun {
 };
 
 struct Batch {
-  Common c;
+  Common c{};
   std::vector<ImgRun> im;
   // prox, prox with residuals, row DFT, column solve, inverse row DFT, and for
   // the reverse sweep the row DFT of the cotangent and its inverse into rb
@@ -513,15 +616,16 @@ size_t desc_size(int which) {
   }
 }
 
+// force (autotuning, one image): plan with these shapes instead of the table's or the planner's.
 segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, const double* lam, const double* mu,
-                           const Common& c, Batch& b) {
+                           const Common& c, Batch& b, const segsalsa_tuning* force = nullptr) {
   b.c = c;
   b.im.resize(n);
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
     segsalsa_status s = validate_image(K[i], H[i], W[i], lam[i], mu[i]);
     if (s != SEGSALSA_OK) return fail(s, "image %d: %s", i, segsalsa_last_error());
-    s = make_image_plan(K[i], H[i], W[i], c, b.im[i].plan);
+    s = force ? plan_with(K[i], H[i], W[i], c, *force, b.im[i].plan) : make_image_plan(K[i], H[i], W[i], c, b.im[i].plan);
     if (s != SEGSALSA_OK) return s;
     b.im[i].base = off;
     b.im[i].lambda = lam[i];
@@ -536,18 +640,22 @@ segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, cons
   return SEGSALSA_OK;
 }
 
-// Launch shapes for the active images: prox launches grouped by workgroup
-// shape, one launch per FFT pass with the largest per-image shape.
+// Launch shapes for the active images: one launch per distinct workgroup
+// shape of each kernel (the prox kernel by wavefronts and classes per
+// wavefront, the FFT passes by threads and elements per thread), over the
+// images of that shape, whose descriptors are contiguous in the tables.
 struct LaunchSet {
   struct Group {
     int kpw, nw, first, count, blocks;
     size_t lds;
   };
+  struct FftGroup {
+    int ept, threads, first, count, blocks;
+    size_t lds;
+  };
   std::vector<Group> groups;
+  std::vector<FftGroup> rgroups, cgroups;
   int nact = 0;
-  int row_blocks = 0, row_threads = 64, row_ept = 2, col_blocks = 0, col_threads = 64, col_ept = 2;
-  bool row_narrow = false, col_narrow = false;  // FP64: the 512-thread FFT instantiations
-  size_t row_lds = 0, col_lds = 0;
 };
 
 template <typename T>
@@ -620,28 +728,37 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const ImgRun& r = b.im[order[q]];
     pb[q].res_tile = wsp<double>(wsp<char>(ws, r.base), r.plan.off_restile);
   }
-  // FFT passes: one launch each over all active images
+  // FFT passes: the row tables (fold + row DFT, inverse row DFT) ordered by
+  // the row workgroup shape, the column table by the column shape
+  std::vector<int> rord(active), cord(active);
+  std::stable_sort(rord.begin(), rord.end(), [&](int x, int y) {
+    const Plan& px = b.im[x].plan;
+    const Plan& py = b.im[y].plan;
+    return px.row_threads != py.row_threads ? px.row_threads < py.row_threads : px.row_ept < py.row_ept;
+  });
+  std::stable_sort(cord.begin(), cord.end(), [&](int x, int y) {
+    const Plan& px = b.im[x].plan;
+    const Plan& py = b.im[y].plan;
+    return px.col_threads != py.col_threads ? px.col_threads < py.col_threads : px.col_ept < py.col_ept;
+  });
   std::vector<RowFwdArgs<T>> rf(active.size());
   std::vector<ColArgs<T>> ca(active.size());
   std::vector<RowInvArgs<T>> ri(active.size());
-  for (const int i : active) {
-    const Plan& p = b.im[i].plan;
-    ls.row_ept = std::max(ls.row_ept, p.row_ept);
-    ls.col_ept = std::max(ls.col_ept, p.col_ept);
+  double wsum = 0.0;
+  for (int j = 0; j < c.L; ++j) {
+    const double cj = (double)(T)c.w[j];  // the multiplier J applies, rounded to T
+    wsum += cj * cj;
   }
-  int rb = 0, cb = 0;
-  for (size_t q = 0; q < active.size(); ++q) {
-    const ImgRun& r = b.im[active[q]];
+  for (size_t q = 0; q < rord.size(); ++q) {
+    const ImgRun& r = b.im[rord[q]];
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
-    double wsum = 0.0;
-    for (int j = 0; j < c.L; ++j) {
-      const double cj = (double)(T)c.w[j];  // the multiplier J applies, rounded to T
-      wsum += cj * cj;
-    }
+    if (ls.rgroups.empty() || ls.rgroups.back().threads != p.row_threads || ls.rgroups.back().ept != p.row_ept)
+      ls.rgroups.push_back({p.row_ept, p.row_threads, (int)q, 0, 0, 0});
+    LaunchSet::FftGroup& g = ls.rgroups.back();
     RowFwdArgs<T>& f = rf[q];
     std::memset(&f, 0, sizeof(f));
-    f.block0 = rb;
+    f.block0 = g.blocks;
     f.g = p.g;
     f.K = p.K;
     f.P = p.P;
@@ -652,70 +769,42 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     f.spec = wsp<C2<T>>(base, p.off_spec);
     f.tab = row_tab<T>(p, base);
     f.plan = p.frow;
+    RowInvArgs<T>& v = ri[q];
+    std::memset(&v, 0, sizeof(v));
+    v.block0 = g.blocks;
+    v.H = p.H; v.W = p.W; v.K = p.K; v.P = p.P;
+    v.rows_per_block = p.rows_per_block;
+    v.spec = f.spec;
+    v.z = reinterpret_cast<T*>(zs[rord[q]]);
+    v.tab = f.tab;
+    v.plan = p.frow;
+    g.count += 1;
+    g.blocks += p.P * ceil_div(p.H, p.rows_per_block);
+    g.lds = std::max(g.lds, p.row_lds);
+  }
+  for (size_t q = 0; q < cord.size(); ++q) {
+    const ImgRun& r = b.im[cord[q]];
+    const Plan& p = r.plan;
+    void* base = wsp<char>(ws, r.base);
+    if (ls.cgroups.empty() || ls.cgroups.back().threads != p.col_threads || ls.cgroups.back().ept != p.col_ept)
+      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0});
+    LaunchSet::FftGroup& g = ls.cgroups.back();
     ColArgs<T>& k = ca[q];
     std::memset(&k, 0, sizeof(k));
-    k.block0 = cb;
+    k.block0 = g.blocks;
     k.H = p.H; k.W = p.W; k.P = p.P;
     k.cols_per_block = p.cols_per_block;
-    k.spec = f.spec;
+    k.spec = wsp<C2<T>>(base, p.off_spec);
     k.tab = col_tab<T>(p, base);
     k.sx = wsp<double>(base, p.off_sx);
     k.sy = wsp<double>(base, p.off_sy);
     k.wsum = wsum;
     k.scale = 1.0 / ((double)p.H * (double)p.W);
     k.plan = p.fcol;
-    RowInvArgs<T>& v = ri[q];
-    std::memset(&v, 0, sizeof(v));
-    v.block0 = rb;
-    v.H = p.H; v.W = p.W; v.K = p.K; v.P = p.P;
-    v.rows_per_block = p.rows_per_block;
-    v.spec = f.spec;
-    v.z = reinterpret_cast<T*>(zs[active[q]]);
-    v.tab = f.tab;
-    v.plan = p.frow;
-    rb += p.P * ceil_div(p.H, p.rows_per_block);
-    cb += p.P * ceil_div(p.W, p.cols_per_block);
-    const long long ritems = (long long)p.rows_per_block * (p.frow.blu ? p.frow.M : p.W);
-    const long long citems = (long long)p.cols_per_block * (p.fcol.blu ? p.fcol.M : p.H);
-    ls.row_threads = std::max<int>(ls.row_threads, (int)((ritems + ls.row_ept - 1) / ls.row_ept));
-    ls.col_threads = std::max<int>(ls.col_threads, (int)((citems + ls.col_ept - 1) / ls.col_ept));
-    ls.row_lds = std::max(ls.row_lds, p.row_lds);
-    ls.col_lds = std::max(ls.col_lds, p.col_lds);
+    g.count += 1;
+    g.blocks += p.P * ceil_div(p.W, p.cols_per_block);
+    g.lds = std::max(g.lds, p.col_lds);
   }
-  ls.row_threads = std::min(kFftMaxThreads, (ls.row_threads + 63) / 64 * 64);
-  ls.col_threads = std::min(kFftMaxThreads, (ls.col_threads + 63) / 64 * 64);
-  if (sizeof(T) == 8) {
-    // FP64: the narrow (512-thread, spill-free) FFT kernels where they measured
-    // faster.  Rows: for a single image (latency-bound passes); a batch keeps
-    // the occupancy of the wide kernels.  Columns: unless they would need more
-    // than 4 elements per thread where the wide sizing stays below 1024 threads.
-    if (active.size() == 1 && b.im[active[0]].plan.row_threads_n > 0) {
-      const Plan& p = b.im[active[0]].plan;
-      ls.row_ept = p.row_ept_n;
-      ls.row_threads = p.row_threads_n;
-      ls.row_narrow = true;
-    }
-    bool fits = true;
-    int ept_n = 2;
-    for (const int i : active) {
-      const Plan& p = b.im[i].plan;
-      if (p.col_threads_n == 0) fits = false;
-      ept_n = std::max(ept_n, p.col_ept_n);
-    }
-    if (fits && (ept_n <= 4 || ls.col_threads == kFftMaxThreads)) {
-      int thr = 64;
-      for (const int i : active) {
-        const Plan& p = b.im[i].plan;
-        const long long citems = (long long)p.cols_per_block * (p.fcol.blu ? p.fcol.M : p.H);
-        thr = std::max<int>(thr, (int)((citems + ept_n - 1) / ept_n));
-      }
-      ls.col_ept = ept_n;
-      ls.col_threads = std::min(kFftNarrowThreads, (thr + 63) / 64 * 64);
-      ls.col_narrow = true;
-    }
-  }
-  ls.row_blocks = rb;
-  ls.col_blocks = cb;
   hipError_t e;
   if (!pa.empty()) {
     if ((e = launch_store(wsp<char>(ws, b.off_tab[0]), pa.data(), pa.size() * sizeof(pa[0]), st)) != hipSuccess) return e;
@@ -724,9 +813,9 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     if ((e = launch_store(wsp<char>(ws, b.off_tab[3]), ca.data(), ca.size() * sizeof(ca[0]), st)) != hipSuccess) return e;
     if ((e = launch_store(wsp<char>(ws, b.off_tab[4]), ri.data(), ri.size() * sizeof(ri[0]), st)) != hipSuccess) return e;
     if (adj_acc && adj_r) {  // reverse sweep: fold the cotangent's partial sums, solve into rb
-      for (size_t q = 0; q < active.size(); ++q) {
-        rf[q].acc = reinterpret_cast<const T*>(adj_acc[active[q]]);
-        ri[q].z = reinterpret_cast<T*>(adj_r[active[q]]);
+      for (size_t q = 0; q < rord.size(); ++q) {
+        rf[q].acc = reinterpret_cast<const T*>(adj_acc[rord[q]]);
+        ri[q].z = reinterpret_cast<T*>(adj_r[rord[q]]);
       }
       if ((e = launch_store(wsp<char>(ws, b.off_tab[5]), rf.data(), rf.size() * sizeof(rf[0]), st)) != hipSuccess)
         return e;
@@ -739,30 +828,55 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
 
 // The z-update solve A z = rhs (eq. (12)) by the three FFT passes, with the
 // row tables `fwd_tab` (fold + row DFT) and `inv_tab` (inverse row DFT).
+// ev (autotuning): if given, ev[0] is recorded after the row DFT pass, ev[1]
+// after the column pass and ev[2] after the inverse row pass.
 template <typename T>
-hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, int fwd_tab, int inv_tab) {
-  hipError_t e;
-  PhaseTimer t1(1, st);
-  e = launch_rows_fwd(wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_narrow, ls.row_lds, st);
-  t1.stop();
-  if (e != hipSuccess) return e;
-  PhaseTimer t2(2, st);
-  e = launch_cols(wsp<ColArgs<T>>(ws, b.off_tab[3]), ls.nact, ls.col_blocks, ls.col_ept, ls.col_threads,
-                  ls.col_narrow, ls.col_lds, st);
-  t2.stop();
-  if (e != hipSuccess) return e;
-  PhaseTimer t3(3, st);
-  e = launch_rows_inv(wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]), ls.nact, ls.row_blocks, ls.row_ept, ls.row_threads,
-                      ls.row_narrow, ls.row_lds, st);
-  t3.stop();
+hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, int fwd_tab, int inv_tab,
+                       hipEvent_t* ev = nullptr) {
+  hipError_t e = hipSuccess;
+  // FP64 workgroups of at most 512 threads run the build with 256 VGPRs
+  auto narrow = [](int threads) { return sizeof(T) == 8 && threads <= kFftNarrowThreads; };
+  {
+    PhaseTimer t1(1, st);
+    const RowFwdArgs<T>* tab = wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]);
+    for (const auto& g : ls.rgroups)
+      if ((e = launch_rows_fwd(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
+          hipSuccess)
+        return e;
+    t1.stop();
+    if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  }
+  {
+    PhaseTimer t2(2, st);
+    const ColArgs<T>* tab = wsp<ColArgs<T>>(ws, b.off_tab[3]);
+    for (const auto& g : ls.cgroups)
+      if ((e = launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
+          hipSuccess)
+        return e;
+    t2.stop();
+    if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+  }
+  {
+    PhaseTimer t3(3, st);
+    const RowInvArgs<T>* tab = wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]);
+    for (const auto& g : ls.rgroups)
+      if ((e = launch_rows_inv(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
+          hipSuccess)
+        return e;
+    t3.stop();
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+  }
   return e;
 }
 
+// ev (autotuning): if given, five events recorded before the prox launches,
+// after them, and after each FFT pass.
 template <typename T>
-hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, bool residuals) {
+hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStream_t st, bool residuals,
+                         hipEvent_t* ev = nullptr) {
   if (ls.nact == 0) return hipSuccess;
   hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
   const ProxArgs<T>* ptab = wsp<ProxArgs<T>>(ws, b.off_tab[residuals ? 1 : 0]);
   {
     PhaseTimer t0(0, st);
@@ -774,7 +888,8 @@ hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStrea
     }
     t0.stop();
   }
-  return enqueue_fft<T>(b, ls, ws, st, 2, 4);
+  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
+  return enqueue_fft<T>(b, ls, ws, st, 2, 4, ev ? ev + 2 : nullptr);
 }
 
 template <typename T>
@@ -977,7 +1092,12 @@ void key_add(std::vector<unsigned char>& k, const void* p, size_t n) {
 
 std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, const void* const* ins) {
   std::vector<unsigned char> k;
-  key_add(k, &b.c, sizeof(b.c));
+  const Common& c = b.c;   // named fields only (no padding bytes, only the L multipliers in use)
+  const int ci[] = {c.fp64 ? 1 : 0, c.M, c.L, c.pkind, c.iters, c.logits, c.every, c.warm, c.graph, c.g4s};
+  key_add(k, ci, sizeof(ci));
+  key_add(k, c.w, sizeof(double) * (size_t)c.L);
+  key_add(k, &c.p, sizeof(c.p));
+  key_add(k, &c.tol, sizeof(c.tol));
   key_add(k, &ws, sizeof(ws));
   for (size_t i = 0; i < b.im.size(); ++i) {
     const ImgRun& r = b.im[i];
@@ -989,10 +1109,11 @@ std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, 
     key_add(k, &zs[i], sizeof(void*));
     key_add(k, &ins[i], sizeof(void*));
   }
-  // plan choices that environment overrides can change
+  // plan choices that the tuning table can change
   for (size_t i = 0; i < b.im.size(); ++i) {
-    key_add(k, &b.im[i].plan.g, sizeof(TileGeom));
-    key_add(k, &b.im[i].plan.kpw, sizeof(int));
+    const Plan& p = b.im[i].plan;
+    const int pi[] = {p.g.ntr, p.g.ntc, p.kpw, p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads};
+    key_add(k, pi, sizeof(pi));
   }
   return k;
 }
@@ -1079,7 +1200,7 @@ segsalsa_status solve_batch_t(const Batch& b, void* ws, void* const* zs, const v
 }
 
 segsalsa_status single_batch(const segsalsa_problem* pr, segsalsa_precision prec, Batch& b) {
-  Common c;
+  Common c{};
   segsalsa_status s = validate_problem(pr, prec, c);
   if (s != SEGSALSA_OK) return s;
   return make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, b);
@@ -1127,7 +1248,7 @@ struct GradLayout {
 };
 
 segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision prec, int every_ck, GradLayout& gl) {
-  Common c;
+  Common c{};
   segsalsa_status s = validate_problem(pr, prec, c);
   if (s != SEGSALSA_OK) return s;
   if (every_ck < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "checkpoint_every = %d < 1", every_ck);
@@ -1287,6 +1408,258 @@ segsalsa_status backward_t(const GradLayout& gl, void* ws, const void* input, co
   return SEGSALSA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning: candidate launch shapes of one image shape, each timed on the
+// device over a few rounds.
+// ---------------------------------------------------------------------------
+
+// Per-round milliseconds of one candidate plan: [0] whole round, [1] prox,
+// [2] row DFT passes (forward and inverse), [3] column pass.
+template <typename T>
+hipError_t time_candidate(const Batch& b, void* ws, void* z, const void* in, hipStream_t st, int rounds,
+                          double out[4]) {
+  LaunchSet ls;
+  void* zs[1] = {z};
+  const void* ins[1] = {in};
+  hipError_t e = enqueue_prepare<T>(b, ws, zs, ins, st, ls, true);
+  if (e != hipSuccess) return e;
+  if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return e;   // warm-up round
+  std::vector<hipEvent_t> ev(5 * (size_t)rounds, nullptr);
+  for (auto& x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) break;
+  if (e == hipSuccess)
+    for (int r = 0; r < rounds && e == hipSuccess; ++r) e = enqueue_round<T>(b, ls, ws, st, false, &ev[5 * (size_t)r]);
+  if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+  for (int q = 0; q < 4; ++q) out[q] = 0.0;
+  for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+    float t[4];
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipEventElapsedTime(&t[q], ev[5 * r + q], ev[5 * r + q + 1]);
+    if (e != hipSuccess) break;
+    out[0] += (double)t[0] + t[1] + t[2] + t[3];
+    out[1] += t[0];
+    out[2] += (double)t[1] + t[3];
+    out[3] += t[2];
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
+  for (int q = 0; q < 4; ++q) out[q] /= rounds;
+  return e;
+}
+
+// Fill every field of a tuning record from a plan.
+void tuning_of(const Plan& p, segsalsa_tuning& t) {
+  t.tile_rows = p.g.TR;
+  t.tile_cols = p.g.TC;
+  t.classes_per_wave = p.kpw;
+  t.rows_per_block = p.rows_per_block;
+  t.row_threads = p.row_threads;
+  t.cols_per_block = p.cols_per_block;
+  t.col_threads = p.col_threads;
+}
+
+segsalsa_status check_tuning_fields(const segsalsa_tuning& t) {
+  auto thr_ok = [](int v) { return v == 0 || (v >= 64 && v <= kFftMaxThreads && v % 64 == 0); };
+  if (t.tile_rows < 0 || t.tile_cols < 0 || (t.tile_rows > 0) != (t.tile_cols > 0))
+    return fail(SEGSALSA_ERR_INVALID_ARG, "tile %dx%d: give both sides > 0 or both 0", t.tile_rows, t.tile_cols);
+  if (t.classes_per_wave != 0 && t.classes_per_wave != 1 && t.classes_per_wave != 2 && t.classes_per_wave != 4)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "classes_per_wave = %d (0, 1, 2 or 4)", t.classes_per_wave);
+  if (t.rows_per_block < 0 || t.cols_per_block < 0)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "rows/cols per block must be >= 0");
+  if (!thr_ok(t.row_threads) || !thr_ok(t.col_threads))
+    return fail(SEGSALSA_ERR_INVALID_ARG, "FFT threads %d / %d: 0 or a multiple of 64 in [64, %d]", t.row_threads,
+                t.col_threads, kFftMaxThreads);
+  if (!std::isfinite(t.us_per_round) || t.us_per_round < 0.0)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "us_per_round = %g", t.us_per_round);
+  return SEGSALSA_OK;
+}
+
+// Parameters of a plain forward solve of one shape, for planning only.
+Common plain_common(int M, segsalsa_precision prec) {
+  Common c{};
+  c.fp64 = prec == SEGSALSA_FP64;
+  c.ts = c.fp64 ? 8 : 4;
+  c.M = M;
+  c.L = (2 * M + 1) * (2 * M + 1);
+  for (int j = 0; j < c.L; ++j) c.w[j] = 1.0;
+  c.pkind = kSchatten1;
+  c.p = 1.0;
+  return c;
+}
+
+segsalsa_status validate_shape(int K, int H, int W, int M, segsalsa_precision prec) {
+  if (prec != SEGSALSA_FP32 && prec != SEGSALSA_FP64) return fail(SEGSALSA_ERR_INVALID_ARG, "bad precision %d", (int)prec);
+  if (M < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "patch_radius = %d < 0", M);
+  if (M > kMaxM) return fail(SEGSALSA_ERR_UNSUPPORTED, "patch_radius = %d > %d", M, kMaxM);
+  return validate_image(K, H, W, 0.0, 1.0);
+}
+
+// Minimal reader of the tuning cache: the value of "key" inside one JSON
+// object's text (a number, or a string for "precision").
+bool json_number(const std::string& obj, const char* key, double& v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t i = obj.find(k);
+  if (i == std::string::npos) return false;
+  i = obj.find(':', i + k.size());
+  if (i == std::string::npos) return false;
+  const char* p = obj.c_str() + i + 1;
+  char* end = nullptr;
+  v = std::strtod(p, &end);
+  return end != p;
+}
+bool json_string(const std::string& obj, const char* key, std::string& v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t i = obj.find(k);
+  if (i == std::string::npos) return false;
+  i = obj.find(':', i + k.size());
+  if (i == std::string::npos) return false;
+  const size_t a = obj.find('"', i + 1);
+  if (a == std::string::npos) return false;
+  const size_t e = obj.find('"', a + 1);
+  if (e == std::string::npos) return false;
+  v = obj.substr(a + 1, e - a - 1);
+  return true;
+}
+
+// Candidate launch shapes of the autotuner for one image shape.
+std::vector<segsalsa_tuning> prox_candidates(int K, int H, int W, const Common& c) {
+  std::vector<segsalsa_tuning> out;
+  for (int kpw : {1, 2, 4}) {
+    segsalsa_tuning t{};
+    t.classes_per_wave = kpw;
+    Plan p;
+    const std::string saved = g_last_error;
+    if (plan_with(K, H, W, c, t, p) != SEGSALSA_OK) {   // this many classes per wavefront do not fit
+      g_last_error = saved;
+      continue;
+    }
+    int n = 0;
+    for (const TileGeom& g : tile_candidates(p)) {
+      if (!fold_lists_fit(g)) continue;
+      segsalsa_tuning u = t;
+      u.tile_rows = g.TR;
+      u.tile_cols = g.TC;
+      out.push_back(u);
+      if (++n == 4) break;
+    }
+  }
+  return out;
+}
+
+template <typename T>
+segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const void* input, void* z, void* ws,
+                           size_t wsb, int rounds, segsalsa_tuning& best, hipStream_t st) {
+  const int K = pr->K, H = pr->H, W = pr->W;
+  const std::string saved = g_last_error;
+  // measure one candidate: false if it does not fit (plan or workspace)
+  auto measure = [&](const segsalsa_tuning& tn, double out[4], segsalsa_status& err) -> bool {
+    Batch b;
+    err = SEGSALSA_OK;
+    if (make_batch(1, &K, &H, &W, &pr->lambda, &pr->mu, c, b, &tn) != SEGSALSA_OK || b.total > wsb) {
+      g_last_error = saved;
+      return false;
+    }
+    void* zs = z;
+    hipError_t e = time_candidate<T>(b, ws, zs, input, st, rounds, out);
+    if (e != hipSuccess) {
+      err = hip_fail(e, "autotune candidate");
+      return false;
+    }
+    return true;
+  };
+  segsalsa_status err = SEGSALSA_OK;
+  double t[4];
+  // the planner's own choice first
+  segsalsa_tuning base{};
+  {
+    Plan p;
+    segsalsa_status s = plan_with(K, H, W, c, segsalsa_tuning{}, p);
+    if (s != SEGSALSA_OK) return s;
+    tuning_of(p, base);
+  }
+  if (!measure(base, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_WORKSPACE, "workspace too small");
+  const double base_round = t[0];
+  segsalsa_tuning cur = base;
+  double cur_round = t[0], cur_rows = t[2], cur_cols = t[3];
+  // 1. prox tile and classes per wavefront, by whole rounds (the tile also sets the fold's reads)
+  for (const segsalsa_tuning& pc : prox_candidates(K, H, W, c)) {
+    segsalsa_tuning cand = cur;
+    cand.tile_rows = pc.tile_rows;
+    cand.tile_cols = pc.tile_cols;
+    cand.classes_per_wave = pc.classes_per_wave;
+    if (!measure(cand, t, err)) {
+      if (err != SEGSALSA_OK) return err;
+      continue;
+    }
+    if (t[0] < cur_round) {
+      cur = cand;
+      cur_round = t[0];
+      cur_rows = t[2];
+      cur_cols = t[3];
+    }
+  }
+  // 2. row DFT blocking, by the two row passes
+  {
+    Plan p;
+    if (plan_with(K, H, W, c, cur, p) != SEGSALSA_OK) return fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
+    const int Lr = p.frow.blu ? p.frow.M : W;
+    segsalsa_tuning win = cur;
+    double win_t = cur_rows;
+    for (int rpb : {1, 2, 3, 4, 6, 8, 12, 16}) {
+      if (rpb > H) break;
+      for (int per : {2, 4, 8, 16}) {
+        segsalsa_tuning cand = cur;
+        cand.rows_per_block = rpb;
+        cand.row_threads = fft_threads_for((long long)rpb * Lr, per);
+        if (cand.rows_per_block == cur.rows_per_block && cand.row_threads == cur.row_threads) continue;
+        if (!measure(cand, t, err)) {
+          if (err != SEGSALSA_OK) return err;
+          continue;
+        }
+        if (t[2] < win_t) {
+          win = cand;
+          win_t = t[2];
+        }
+      }
+    }
+    cur = win;
+  }
+  // 3. column blocking, by the column pass
+  {
+    Plan p;
+    if (plan_with(K, H, W, c, cur, p) != SEGSALSA_OK) return fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
+    const int Lc = p.fcol.blu ? p.fcol.M : H;
+    segsalsa_tuning win = cur;
+    double win_t = cur_cols;
+    for (int cb : {1, 2, 4, 8, 16, 32}) {
+      if (cb > W) break;
+      for (int per : {2, 4, 8, 16}) {
+        segsalsa_tuning cand = cur;
+        cand.cols_per_block = cb;
+        cand.col_threads = fft_threads_for((long long)cb * Lc, per);
+        if (cand.cols_per_block == cur.cols_per_block && cand.col_threads == cur.col_threads) continue;
+        if (!measure(cand, t, err)) {
+          if (err != SEGSALSA_OK) return err;
+          continue;
+        }
+        if (t[3] < win_t) {
+          win = cand;
+          win_t = t[3];
+        }
+      }
+    }
+    cur = win;
+  }
+  // the combination, against the planner's choice measured again
+  if (!measure(cur, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
+  double tuned_round = t[0];
+  if (!measure(base, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
+  const double base_again = std::min(base_round, t[0]);
+  best = tuned_round <= base_again ? cur : base;
+  best.us_per_round = 1e3 * std::min(tuned_round, base_again);
+  g_last_error = saved;
+  return SEGSALSA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1341,7 +1714,7 @@ static segsalsa_status batch_common(int32_t n, const segsalsa_image* imgs, const
                                     segsalsa_precision precision, Batch& b) {
   if (n < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "n_images = %d < 1", n);
   if (!imgs || !bp) return fail(SEGSALSA_ERR_INVALID_ARG, "images / params is NULL");
-  Common c;
+  Common c{};
   segsalsa_status s = validate_common(bp->patch_radius, bp->patch_weights, bp->schatten_p, bp->iters,
                                       bp->input_is_logits, bp->residual_every, bp->tol, bp->warm_start, bp->use_graph,
                                       bp->g4_simplex, precision, c);
@@ -1539,5 +1912,175 @@ segsalsa_status segsalsa_profile_read(double* ms, int64_t* launches, int32_t res
   return SEGSALSA_OK;
 }
 
+
+segsalsa_status segsalsa_tuning_set(int32_t K, int32_t H, int32_t W, int32_t patch_radius,
+                                    segsalsa_precision precision, const segsalsa_tuning* tuning) {
+  g_last_error.clear();
+  segsalsa_status s = validate_shape(K, H, W, patch_radius, precision);
+  if (s != SEGSALSA_OK) return s;
+  const TuneKey key{K, H, W, patch_radius, precision == SEGSALSA_FP64 ? 1 : 0};
+  if (!tuning) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.erase(key);
+    return SEGSALSA_OK;
+  }
+  if ((s = check_tuning_fields(*tuning)) != SEGSALSA_OK) return s;
+  Plan p;
+  if ((s = plan_with(K, H, W, plain_common(patch_radius, precision), *tuning, p)) != SEGSALSA_OK) return s;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = *tuning;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_tuning_get(int32_t K, int32_t H, int32_t W, int32_t patch_radius,
+                                    segsalsa_precision precision, segsalsa_tuning* out, int32_t* tuned) {
+  g_last_error.clear();
+  if (!out) return fail(SEGSALSA_ERR_INVALID_ARG, "out is NULL");
+  segsalsa_status s = validate_shape(K, H, W, patch_radius, precision);
+  if (s != SEGSALSA_OK) return s;
+  Plan p;
+  if ((s = make_image_plan(K, H, W, plain_common(patch_radius, precision), p)) != SEGSALSA_OK) return s;
+  segsalsa_tuning t{};
+  tuning_of(p, t);
+  segsalsa_tuning ent{};
+  if (p.tuned && tuning_lookup(K, H, W, patch_radius, precision == SEGSALSA_FP64, ent)) t.us_per_round = ent.us_per_round;
+  *out = t;
+  if (tuned) *tuned = p.tuned ? 1 : 0;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_tuning_clear(void) {
+  g_last_error.clear();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_tuning_save(const char* path) {
+  g_last_error.clear();
+  if (!path) return fail(SEGSALSA_ERR_INVALID_ARG, "path is NULL");
+  std::string txt = "{\n  \"format\": \"segsalsa-tuning-1\",\n  \"entries\": [";
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    bool first = true;
+    for (const auto& kv : g_tune) {
+      const TuneKey& k = kv.first;
+      const segsalsa_tuning& t = kv.second;
+      char buf[512];
+      std::snprintf(buf, sizeof(buf),
+                    "%s\n    {\"K\": %d, \"H\": %d, \"W\": %d, \"M\": %d, \"precision\": \"%s\", \"tile_rows\": %d, "
+                    "\"tile_cols\": %d, \"classes_per_wave\": %d, \"rows_per_block\": %d, \"row_threads\": %d, "
+                    "\"cols_per_block\": %d, \"col_threads\": %d, \"us_per_round\": %.3f}",
+                    first ? "" : ",", k.K, k.H, k.W, k.M, k.fp64 ? "fp64" : "fp32", t.tile_rows, t.tile_cols,
+                    t.classes_per_wave, t.rows_per_block, t.row_threads, t.cols_per_block, t.col_threads,
+                    t.us_per_round);
+      txt += buf;
+      first = false;
+    }
+  }
+  txt += "\n  ]\n}\n";
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SEGSALSA_ERR_INVALID_ARG, "cannot write %s", path);
+  const bool ok = std::fwrite(txt.data(), 1, txt.size(), f) == txt.size();
+  if (std::fclose(f) != 0 || !ok) return fail(SEGSALSA_ERR_INVALID_ARG, "cannot write %s", path);
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_tuning_load(const char* path, int32_t* loaded, int32_t* skipped) {
+  g_last_error.clear();
+  if (loaded) *loaded = 0;
+  if (skipped) *skipped = 0;
+  if (!path) return fail(SEGSALSA_ERR_INVALID_ARG, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SEGSALSA_ERR_INVALID_ARG, "cannot read %s", path);
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+  std::fclose(f);
+  std::string fmt;
+  if (!json_string(txt, "format", fmt) || fmt != "segsalsa-tuning-1")
+    return fail(SEGSALSA_ERR_INVALID_ARG, "%s is not a segsalsa tuning cache", path);
+  size_t pos = txt.find("\"entries\"");
+  if (pos == std::string::npos) return fail(SEGSALSA_ERR_INVALID_ARG, "%s has no entries", path);
+  int nl = 0, ns = 0;
+  while ((pos = txt.find('{', pos)) != std::string::npos) {
+    const size_t end = txt.find('}', pos);
+    if (end == std::string::npos) break;
+    const std::string obj = txt.substr(pos, end - pos + 1);
+    pos = end + 1;
+    double K, H, W, M, tr, tc, kpw, rpb, rt, cpb, ct, us = 0.0;
+    std::string prec;
+    if (!(json_number(obj, "K", K) && json_number(obj, "H", H) && json_number(obj, "W", W) &&
+          json_number(obj, "M", M) && json_string(obj, "precision", prec) && json_number(obj, "tile_rows", tr) &&
+          json_number(obj, "tile_cols", tc) && json_number(obj, "classes_per_wave", kpw) &&
+          json_number(obj, "rows_per_block", rpb) && json_number(obj, "row_threads", rt) &&
+          json_number(obj, "cols_per_block", cpb) && json_number(obj, "col_threads", ct)) ||
+        (prec != "fp32" && prec != "fp64")) {
+      ++ns;
+      continue;
+    }
+    (void)json_number(obj, "us_per_round", us);
+    segsalsa_tuning t{};
+    t.tile_rows = (int)tr; t.tile_cols = (int)tc; t.classes_per_wave = (int)kpw;
+    t.rows_per_block = (int)rpb; t.row_threads = (int)rt; t.cols_per_block = (int)cpb; t.col_threads = (int)ct;
+    t.us_per_round = us;
+    if (segsalsa_tuning_set((int)K, (int)H, (int)W, (int)M, prec == "fp64" ? SEGSALSA_FP64 : SEGSALSA_FP32, &t) ==
+        SEGSALSA_OK)
+      ++nl;
+    else
+      ++ns;
+  }
+  g_last_error.clear();
+  if (loaded) *loaded = nl;
+  if (skipped) *skipped = ns;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_autotune_workspace_size(const segsalsa_problem* prob, segsalsa_precision precision,
+                                                     size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(SEGSALSA_ERR_INVALID_ARG, "bytes is NULL");
+  Common c{};
+  segsalsa_status s = validate_problem(prob, precision, c);
+  if (s != SEGSALSA_OK) return s;
+  c.every = 0; c.tol = 0.0; c.warm = 0; c.graph = 0;
+  size_t best = 0;
+  std::vector<segsalsa_tuning> cands = prox_candidates(prob->K, prob->H, prob->W, c);
+  cands.push_back(segsalsa_tuning{});
+  for (const segsalsa_tuning& t : cands) {
+    Batch b;
+    if (make_batch(1, &prob->K, &prob->H, &prob->W, &prob->lambda, &prob->mu, c, b, &t) == SEGSALSA_OK)
+      best = std::max(best, b.total);
+  }
+  g_last_error.clear();
+  if (best == 0) return fail(SEGSALSA_ERR_UNSUPPORTED, "no launch shape fits this problem");
+  *bytes = best;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_autotune(const segsalsa_problem* prob, segsalsa_precision precision,
+                                      const void* input, void* z_scratch, void* workspace, size_t workspace_bytes,
+                                      int32_t rounds, segsalsa_tuning* best, hipStream_t stream) {
+  g_last_error.clear();
+  Common c{};
+  segsalsa_status s = validate_problem(prob, precision, c);
+  if (s != SEGSALSA_OK) return s;
+  if (rounds < 1 || rounds > 100) return fail(SEGSALSA_ERR_INVALID_ARG, "rounds = %d not in [1, 100]", rounds);
+  if (!input || !z_scratch) return fail(SEGSALSA_ERR_INVALID_ARG, "input / z_scratch is NULL");
+  if (input == z_scratch) return fail(SEGSALSA_ERR_INVALID_ARG, "z_scratch aliases input");
+  if (reinterpret_cast<uintptr_t>(z_scratch) % c.ts || reinterpret_cast<uintptr_t>(input) % c.ts)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "input/z_scratch not aligned to the element size");
+  if ((s = check_ws(1, workspace, workspace_bytes)) != SEGSALSA_OK) return s;
+  c.every = 0; c.tol = 0.0; c.warm = 0; c.graph = 0;
+  segsalsa_tuning win{};
+  s = c.fp64 ? autotune_t<double>(prob, c, input, z_scratch, workspace, workspace_bytes, rounds, win, stream)
+             : autotune_t<float>(prob, c, input, z_scratch, workspace, workspace_bytes, rounds, win, stream);
+  if (s != SEGSALSA_OK) return s;
+  if ((s = segsalsa_tuning_set(prob->K, prob->H, prob->W, prob->patch_radius, precision, &win)) != SEGSALSA_OK)
+    return s;
+  if (best) *best = win;
+  return SEGSALSA_OK;
+}
 
 }  // extern "C"

@@ -451,8 +451,9 @@ template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc)];
-  const int bid = blockIdx.x - a.block0;
+  const int blk = xcd_block();   // consecutive rows (neighbouring grown-tile rows) on one XCD
+  const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
+  const int bid = blk - a.block0;
   const int H = a.g.H, W = a.g.W;
   const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
   const int m = bid / nrb;
@@ -469,24 +470,24 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   // >= nb * W, as the LDS FFT needs): unrolled, so the list and data loads of
   // its elements are in flight together.  The first two entries of each list
   // are read with its count (the lists are kFoldStride > 2 ints long) and
-  // used only below the count.
+  // used only below the count (the table has kFoldStride rows).
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < nb * W) {
       const int rr = idx / W, c = idx - rr * W;
-      const int* rl = a.frow + (size_t)(row0 + rr) * kFoldStride;
-      const int* cl = a.fcol + (size_t)c * kFoldStride;
+      const int* rl = a.frow + (row0 + rr);   // [kFoldStride][H]
+      const int* cl = a.fcol + c;             // [kFoldStride][W]
       const int nr = rl[0], nc = cl[0];
-      const int r0e = rl[1], r1e = rl[2], c0e = cl[1], c1e = cl[2];
+      const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[W], c1e = cl[2 * W];
       T s0 = T(0), s1 = T(0);
       for (int i = 0; i < nr; ++i) {
-        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[1 + i]);
-        const int tr = ri >> 8, er = ri & 255;
+        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[(size_t)(1 + i) * H]);
+        const int tr = ri >> kFoldShift, er = ri & kFoldMask;
         for (int j = 0; j < nc; ++j) {
-          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[1 + j]);
-          const size_t tile = (size_t)tr * a.g.ntc + (cj >> 8);
-          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & 255);
+          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[(size_t)(1 + j) * W]);
+          const size_t tile = (size_t)tr * a.g.ntc + (cj >> kFoldShift);
+          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & kFoldMask);
           s0 += a.acc[off];
           if (has1) s1 += a.acc[off + plane];
         }
@@ -504,8 +505,9 @@ template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const ColArgs<T>& a = descs[find_desc(descs, ndesc)];
-  const int bid = blockIdx.x - a.block0;
+  const int blk = xcd_block();   // adjacent column blocks (shared cache lines) on one XCD
+  const ColArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
+  const int bid = blk - a.block0;
   const int H = a.H, W = a.W;
   const int CB = a.cols_per_block;
   const int ncb = (W + CB - 1) / CB;
@@ -544,8 +546,9 @@ template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
-  const RowInvArgs<T>& a = descs[find_desc(descs, ndesc)];
-  const int bid = blockIdx.x - a.block0;
+  const int blk = xcd_block();
+  const RowInvArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
+  const int bid = blk - a.block0;
   const int H = a.H, W = a.W;
   const int nrb = (H + a.rows_per_block - 1) / a.rows_per_block;
   const int m = bid / nrb;

@@ -45,14 +45,8 @@ __global__ void setup_kernel(const SetupArgs<T> a) {
     a.twMH[t] = C2<T>{T(c), T(-s)};
   }
   // fold lists (the host checked that none overflows)
-  if (t < a.H) {
-    int* o = a.frow + (size_t)t * kFoldStride;
-    o[0] = fold_list(a.g, t, true, o + 1);
-  }
-  if (t < a.W) {
-    int* o = a.fcol + (size_t)t * kFoldStride;
-    o[0] = fold_list(a.g, t, false, o + 1);
-  }
+  if (t < a.H) a.frow[t] = fold_list(a.g, t, true, a.frow + a.H + t, a.H);
+  if (t < a.W) a.fcol[t] = fold_list(a.g, t, false, a.fcol + a.W + t, a.W);
 }
 
 template <typename T>

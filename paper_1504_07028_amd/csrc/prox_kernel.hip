@@ -35,9 +35,10 @@ __global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
   constexpr int L = D * D;
-  const ProxArgs<T>& a = descs[find_desc(descs, ndesc)];
+  const int blk = xcd_block();   // neighbouring tiles (shared halo rows) on one XCD
+  const ProxArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
   const TileGeom& g = a.g;
-  const int tile = blockIdx.x - a.block0;
+  const int tile = blk - a.block0;
   const int tr = tile / g.ntc;
   const int tc = tile - tr * g.ntc;
   const int r0 = g.r0(tr), c0 = g.c0(tc);
@@ -313,12 +314,12 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       glob(a.res_tile)[tile] = t;
     }
   }
-  const gptr<T> blk = glob(a.acc) + (size_t)tile * K * g.ER * g.EC;
+  const gptr<T> out = glob(a.acc) + (size_t)tile * K * g.ER * g.EC;
   for (int idx = threadIdx.x; idx < K * plane; idx += blockDim.x) {
     const int k = idx / plane;
     const int rem = idx - k * plane;
     const int er = rem / EC, ec = rem - er * EC;
-    blk[((size_t)k * g.ER + er) * g.EC + ec] = acc[idx];
+    out[((size_t)k * g.ER + er) * g.EC + ec] = acc[idx];
   }
 }
 

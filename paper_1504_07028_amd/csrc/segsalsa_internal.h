@@ -87,12 +87,19 @@ __host__ __device__ inline void tile_pos(const TileGeom& g, int r, int c, int& t
 // partial sums at every grown position that maps onto x periodically.  A
 // source row r_s scatters to r_s + [-M, M+1], so only tiles holding a source
 // row in x - M - 1 .. x + M contribute.  fold_list writes those positions as
-// tile_row * 256 + e (e = position inside the grown tile) and returns their
-// number, or -1 if there are more than kFoldMax.
+// (tile_row << kFoldShift) | e (e = position inside the grown tile) to
+// out[0], out[stride], out[2 stride], ... and returns their number, or -1 if
+// there are more than kFoldMax.  The lists of all rows (columns) are stored
+// structure-of-arrays, [kFoldStride][n] with the count first, so that the
+// lanes of a wavefront reading the lists of consecutive columns read
+// consecutive words.
 constexpr int kFoldMax = 16;
-constexpr int kFoldStride = kFoldMax + 1;   // [count, entries...] per row / column
+constexpr int kFoldStride = kFoldMax + 1;   // count + entries per row / column
+constexpr int kFoldShift = 13;              // e < ER, EC <= kMaxSide + 2 kMaxM + 1 < 2^13
+constexpr int kFoldMask = (1 << kFoldShift) - 1;
+static_assert(kMaxSide + 2 * kMaxM + 1 <= kFoldMask, "grown tile position must fit the fold encoding");
 
-__host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, int* out) {
+__host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, int* out, int stride) {
   const int n = is_row ? g.H : g.W;
   const int M = g.M;
   int cnt = 0;
@@ -109,11 +116,24 @@ __host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, 
     const int lim = (is_row ? g.th(t) : g.tw(t)) + 2 * M;
     for (int e = wrap_index(x - o + M, n); e <= lim; e += n) {
       if (cnt >= kFoldMax) return -1;
-      if (out) out[cnt] = t * 256 + e;
+      if (out) out[(size_t)cnt * stride] = (t << kFoldShift) | e;
       ++cnt;
     }
   }
   return cnt;
+}
+
+// Workgroups of a launch are dealt to the eight XCDs of the chip round-robin
+// (workgroup i runs on XCD i mod 8), and each XCD has its own L2.  Kernels
+// whose neighbouring work items share cache lines (the halos of adjacent
+// tiles, the adjacent column blocks of one row) renumber their workgroups so
+// that each XCD gets one contiguous range of work items.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block() {
+  const int n = gridDim.x, i = blockIdx.x;
+  const int q = n / kXcds, r = n - q * kXcds;
+  const int x = i % kXcds, j = i / kXcds;
+  return x * q + (x < r ? x : r) + j;
 }
 
 // Per-pixel arithmetic parameters of one round.
@@ -122,8 +142,7 @@ enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3, kSchattenP 
 // Per-image kernel arguments live in device tables; a launch covers a range
 // of images and block b belongs to the last image whose block0 <= b.
 template <typename D>
-__device__ inline int find_desc(const D* descs, int n) {
-  const int b = blockIdx.x;
+__device__ inline int find_desc(const D* descs, int n, int b) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -182,8 +201,8 @@ struct RowFwdArgs {
   int K, P;
   int rows_per_block;
   const T* __restrict__ acc;    // per-tile partial sums
-  const int* __restrict__ frow; // [H][kFoldStride] fold lists of rows
-  const int* __restrict__ fcol; // [W][kFoldStride] fold lists of columns
+  const int* __restrict__ frow; // [kFoldStride][H] fold lists of rows
+  const int* __restrict__ fcol; // [kFoldStride][W] fold lists of columns
   C2<T>* __restrict__ spec;     // [P][H][W]
   FftTab<T> tab;                // row-length tables
   FftPlanDev plan;

@@ -63,8 +63,8 @@ hipError_t launch_rows_inv(const RowInvArgs<double>* d, int n, int blocks, int e
 template <typename T>
 struct SetupArgs {
   TileGeom g;
-  int* frow;    // [H][kFoldStride]
-  int* fcol;    // [W][kFoldStride]
+  int* frow;    // [kFoldStride][H]
+  int* fcol;    // [kFoldStride][W]
   int H, W;
   C2<T>* twW;   // exp(-2 pi i t / W), t < W
   C2<T>* twH;   // exp(-2 pi i t / H), t < H

@@ -53,6 +53,19 @@ class segsalsa_batch_params(ctypes.Structure):
                 ("warm_start", c_int32), ("use_graph", c_int32), ("g4_simplex", c_int32)]
 
 
+class segsalsa_tuning(ctypes.Structure):
+    _fields_ = [("tile_rows", c_int32), ("tile_cols", c_int32), ("classes_per_wave", c_int32),
+                ("rows_per_block", c_int32), ("row_threads", c_int32), ("cols_per_block", c_int32),
+                ("col_threads", c_int32), ("us_per_round", c_double)]
+
+
+TUNING_FIELDS = ("tile_rows", "tile_cols", "classes_per_wave", "rows_per_block", "row_threads", "cols_per_block",
+                 "col_threads", "us_per_round")
+# Launch shapes measured by segsalsa_str_autotune on an MI355X for the shapes
+# the benchmark and the tests run (written by `python -m paper_1504_07028_amd.autotune`).
+DEFAULT_TUNING_CACHE = os.path.join(_HERE, "tuning", "mi355x_gfx950.json")
+
+
 class segsalsa_stats(ctypes.Structure):
     _fields_ = [("primal_res", c_double), ("dual_res", c_double), ("objective", c_double),
                 ("rounds_done", c_int32), ("flags", c_int32)]
@@ -104,7 +117,25 @@ def lib():
     L.segsalsa_profile_enable.restype = c_int32
     L.segsalsa_profile_read.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), c_int32]
     L.segsalsa_profile_read.restype = c_int32
+    shape = [c_int32, c_int32, c_int32, c_int32, c_int32]
+    L.segsalsa_tuning_set.argtypes = shape + [POINTER(segsalsa_tuning)]
+    L.segsalsa_tuning_set.restype = c_int32
+    L.segsalsa_tuning_get.argtypes = shape + [POINTER(segsalsa_tuning), POINTER(c_int32)]
+    L.segsalsa_tuning_get.restype = c_int32
+    L.segsalsa_tuning_clear.argtypes = []
+    L.segsalsa_tuning_clear.restype = c_int32
+    L.segsalsa_tuning_load.argtypes = [c_char_p, POINTER(c_int32), POINTER(c_int32)]
+    L.segsalsa_tuning_load.restype = c_int32
+    L.segsalsa_tuning_save.argtypes = [c_char_p]
+    L.segsalsa_tuning_save.restype = c_int32
+    L.segsalsa_str_autotune_workspace_size.argtypes = [POINTER(segsalsa_problem), c_int32, POINTER(c_size_t)]
+    L.segsalsa_str_autotune_workspace_size.restype = c_int32
+    L.segsalsa_str_autotune.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                        c_int32, POINTER(segsalsa_tuning), c_void_p]
+    L.segsalsa_str_autotune.restype = c_int32
     _lib = L
+    if os.path.exists(DEFAULT_TUNING_CACHE) and not os.environ.get("SEGSALSA_NO_TUNING_CACHE"):
+        segsalsa_tuning_load(DEFAULT_TUNING_CACHE)
     return L
 
 
@@ -306,6 +337,61 @@ def segsalsa_str_backward(problem: Problem, checkpoint_every: int, inp, grad_z, 
         _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(), _stream(stream)))
 
 
+def _tuning_dict(t):
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def segsalsa_tuning_set(K, H, W, patch_radius, precision, tuning=None):
+    """Set the tuned launch shapes of one image shape (a dict of TUNING_FIELDS; None removes the entry)."""
+    t = None
+    if tuning is not None:
+        t = segsalsa_tuning(*[int(tuning.get(f, 0)) for f in TUNING_FIELDS[:-1]],
+                            float(tuning.get("us_per_round", 0.0)))
+    _check(lib().segsalsa_tuning_set(K, H, W, patch_radius, int(precision), ctypes.byref(t) if t is not None else None))
+
+
+def segsalsa_tuning_get(K, H, W, patch_radius, precision):
+    """(launch shapes the planner uses for this image shape, whether they come from the tuning table)."""
+    t = segsalsa_tuning()
+    tuned = c_int32(0)
+    _check(lib().segsalsa_tuning_get(K, H, W, patch_radius, int(precision), ctypes.byref(t), ctypes.byref(tuned)))
+    return _tuning_dict(t), bool(tuned.value)
+
+
+def segsalsa_tuning_clear():
+    _check(lib().segsalsa_tuning_clear())
+
+
+def segsalsa_tuning_load(path):
+    """Add the entries of a JSON tuning cache to the table; returns (loaded, skipped)."""
+    a, b = c_int32(0), c_int32(0)
+    _check(lib().segsalsa_tuning_load(os.fsencode(path), ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def segsalsa_tuning_save(path):
+    _check(lib().segsalsa_tuning_save(os.fsencode(path)))
+
+
+def segsalsa_str_autotune_workspace_size(problem: Problem, precision: int) -> int:
+    n = c_size_t(0)
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_autotune_workspace_size(ctypes.byref(s), int(precision), ctypes.byref(n)))
+    return int(n.value)
+
+
+def segsalsa_str_autotune(problem: Problem, inp, z_scratch, workspace, rounds=5, stream=None):
+    """Measure launch shapes for the problem's image shape; stores the fastest in the tuning table and returns it."""
+    nel = problem.K * problem.H * problem.W
+    s = problem.c_struct()
+    t = segsalsa_tuning()
+    _check(lib().segsalsa_str_autotune(ctypes.byref(s), _prec(z_scratch.dtype), _dev_ptr(inp, "input", z_scratch.dtype, nel),
+                                       _dev_ptr(z_scratch, "z_scratch", None, nel),
+                                       _dev_ptr(workspace, "workspace", torch.uint8), workspace.numel(), int(rounds),
+                                       ctypes.byref(t), _stream(stream)))
+    return _tuning_dict(t)
+
+
 class SegSalsaSTR(torch.autograd.Function):
     """z = SegSALSA-STR(input; lambda, c) as an autograd function.
 
@@ -329,6 +415,9 @@ class SegSalsaSTR(torch.autograd.Function):
         ctx.pr, ctx.ck, ctx.ws = pr, checkpoint_every, ws
         ctx.lam_is_tensor = isinstance(lam, torch.Tensor)
         ctx.w_is_tensor = isinstance(weights, torch.Tensor)
+        # gradients go back on the device and in the dtype of the tensors given
+        ctx.lam_like = (lam.device, lam.dtype) if ctx.lam_is_tensor else None
+        ctx.w_like = (weights.device, weights.dtype) if ctx.w_is_tensor else None
         ctx.save_for_backward(inp)
         return z
 
@@ -342,8 +431,9 @@ class SegSalsaSTR(torch.autograd.Function):
         gw = torch.empty(L, dtype=torch.float64, device=inp.device)
         segsalsa_str_backward(pr, ctx.ck, inp, gz.contiguous(), gi, ctx.ws, gl, gw)
         ctx.ws = None
-        return (gi, gl[0] if ctx.lam_is_tensor else None, gw if ctx.w_is_tensor else None,
-                None, None, None, None, None, None)
+        glam = gl[0].to(device=ctx.lam_like[0], dtype=ctx.lam_like[1]) if ctx.lam_is_tensor else None
+        gwt = gw.to(device=ctx.w_like[0], dtype=ctx.w_like[1]) if ctx.w_is_tensor else None
+        return (gi, glam, gwt, None, None, None, None, None, None)
 
 
 PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "adjoint_prox")

@@ -225,8 +225,53 @@ def objective_dense(zvec, phat, Jm, K, n, L, lam, pchoice):
     for i in range(n):
         B = Jz[:, :, :, i].transpose(0, 2, 1).reshape(L * K, 2)
         S = np.linalg.svd(B, compute_uv=False)
-        val += lam * (S.sum() if pchoice == 1 else (np.linalg.norm(S) if pchoice == 2 else S.max()))
+        if pchoice == 1:
+            nrm = S.sum()
+        elif pchoice == 2:
+            nrm = np.linalg.norm(S)
+        elif math.isinf(pchoice):
+            nrm = S.max()
+        else:   # general p >= 1: the l_p norm of the singular values, written out
+            nrm = sum(float(x) ** pchoice for x in S) ** (1.0 / pchoice)
+        val += lam * nrm
     return float(val)
+
+
+def lq_ball_proj_2d(S, q, rad, grid=2049, refine=90):
+    """Projection of nonnegative 2-vectors (rows of S) onto {y : y1^q + y2^q <= rad^q}, 1 < q < inf.
+
+    Outside the ball the projection lies on its boundary, which in the first quadrant is
+    y(t) = rad (cos(t)^(2/q), sin(t)^(2/q)), t in [0, pi/2].  The squared distance to y(t)
+    is minimised on a dense grid of t, then refined by golden-section search inside the
+    bracket around the best grid point.
+    """
+    S = np.asarray(S, dtype=float)
+    out = S.copy()
+    outside = np.sum(S ** q, axis=1) > rad ** q
+    if not np.any(outside):
+        return out
+    w = S[outside]
+
+    def dist(t):
+        c = np.cos(t) ** (2.0 / q)
+        s = np.sin(t) ** (2.0 / q)
+        return (rad * c - w[:, :1]) ** 2 + (rad * s - w[:, 1:2]) ** 2
+
+    ts = np.linspace(0.0, 0.5 * math.pi, grid)[None, :]
+    i = np.argmin(dist(ts), axis=1)
+    h = 0.5 * math.pi / (grid - 1)
+    a = np.clip(ts[0, i] - h, 0.0, 0.5 * math.pi)[:, None]
+    b = np.clip(ts[0, i] + h, 0.0, 0.5 * math.pi)[:, None]
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    for _ in range(refine):
+        c1 = b - g * (b - a)
+        c2 = a + g * (b - a)
+        left = dist(c1) < dist(c2)
+        b = np.where(left, c2, b)
+        a = np.where(left, a, c1)
+    t = 0.5 * (a + b)
+    out[outside] = np.hstack([rad * np.cos(t) ** (2.0 / q), rad * np.sin(t) ** (2.0 / q)])
+    return out
 
 
 def pdhg(phat, c, M, pchoice, lam, iters):
@@ -235,7 +280,7 @@ def pdhg(phat, c, M, pchoice, lam, iters):
     min_z  F(A z) + i_simplex(z),  A = [I; J] (dense J from index arithmetic),
     F(a, b) = sum_i -ln(p_i^T a_i) + lam sum_i ||b_i||_{S_p}.
     Dual prox of the Schatten part = projection of the singular values onto
-    the dual-norm ball (S_inf, S_2 or S_1 ball of radius lam); dual prox of the
+    the dual-norm ball (S_inf, S_2, S_1 or, for general p, S_q ball of radius lam); dual prox of the
     data part by Moreau's identity with the closed-form primal prox.
     Returns (z, objective at z).
     """
@@ -266,6 +311,9 @@ def pdhg(phat, c, M, pchoice, lam, iters):
         elif pchoice == 2:
             nr = np.linalg.norm(S, axis=1, keepdims=True)
             S2 = S * np.minimum(1.0, lam / np.where(nr > 0, nr, 1.0))
+        elif not math.isinf(pchoice):
+            # general p: the dual norm ball is the l_q ball, 1/p + 1/q = 1
+            S2 = lq_ball_proj_2d(S, pchoice / (pchoice - 1.0), lam)
         else:
             lo = np.zeros(n)
             hi = S.max(axis=1)

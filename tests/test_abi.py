@@ -215,3 +215,113 @@ def test_shapes_beyond_one_workgroup_are_unsupported(S):
     assert status_of_size(S, base_problem(S, K=33, H=20, W=20, **pw25))[0] == UNSUPPORTED
     assert status_of_size(S, base_problem(S, K=16, H=20, W=20, **pw25), prec=1)[0] == OK
     assert status_of_size(S, base_problem(S, K=17, H=20, W=20, **pw25), prec=1)[0] == UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# Tuning table and cache (host side)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture()
+def clean_table(S):
+    S.segsalsa_tuning_clear()
+    yield S
+    S.segsalsa_tuning_clear()
+    if os.path.exists(S.DEFAULT_TUNING_CACHE):
+        S.segsalsa_tuning_load(S.DEFAULT_TUNING_CACHE)
+
+
+def test_tuning_set_get_and_workspace(clean_table):
+    S = clean_table
+    K, H, W, M = 4, 40, 60, 1
+    plan, tuned = S.segsalsa_tuning_get(K, H, W, M, 0)
+    assert not tuned and plan["tile_rows"] > 0 and plan["row_threads"] % 64 == 0
+    st, before = status_of_size(S, base_problem(S, K=K, H=H, W=W))
+    assert st == OK
+    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, rows_per_block=3, row_threads=128, cols_per_block=4,
+                col_threads=192, us_per_round=12.5)
+    S.segsalsa_tuning_set(K, H, W, M, 0, want)
+    got, tuned = S.segsalsa_tuning_get(K, H, W, M, 0)
+    assert tuned and got == want
+    # the tile grid changed, so the workspace did too; FP64 of the same shape is untouched
+    st, after = status_of_size(S, base_problem(S, K=K, H=H, W=W))
+    assert st == OK and after != before
+    assert not S.segsalsa_tuning_get(K, H, W, M, 1)[1]
+    S.segsalsa_tuning_set(K, H, W, M, 0, None)
+    assert not S.segsalsa_tuning_get(K, H, W, M, 0)[1]
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(tile_rows=4), INVALID),                         # one side only
+    (dict(classes_per_wave=3), INVALID),
+    (dict(row_threads=100), INVALID),                     # not a multiple of 64
+    (dict(col_threads=2048), INVALID),
+    (dict(tile_rows=40, tile_cols=60, classes_per_wave=1), UNSUPPORTED),   # grown tile beyond LDS
+    (dict(rows_per_block=40, row_threads=64), UNSUPPORTED),               # 40 x 60 elements > 16 per thread
+])
+def test_tuning_rejects_entries_that_do_not_fit(clean_table, bad, code):
+    S = clean_table
+    with pytest.raises(S.SegsalsaError) as e:
+        S.segsalsa_tuning_set(16, 40, 60, 2, 0, bad)
+    assert e.value.status == code
+    assert not S.segsalsa_tuning_get(16, 40, 60, 2, 0)[1]
+
+
+def test_tile_positions_beyond_256_are_encoded(clean_table):
+    """A grown tile wider than 256 columns (fold-list positions above 255) is a valid tuned shape."""
+    S = clean_table
+    S.segsalsa_tuning_set(2, 8, 300, 0, 0, dict(tile_rows=2, tile_cols=300))
+    got, tuned = S.segsalsa_tuning_get(2, 8, 300, 0, 0)
+    assert tuned and got["tile_cols"] == 300
+
+
+def test_tuning_cache_round_trip(clean_table, tmp_path):
+    S = clean_table
+    S.segsalsa_tuning_set(9, 61, 34, 2, 0, dict(tile_rows=8, tile_cols=17, classes_per_wave=1))
+    S.segsalsa_tuning_set(16, 145, 145, 2, 1, dict(rows_per_block=2, row_threads=128, us_per_round=99.0))
+    path = tmp_path / "cache.json"
+    S.segsalsa_tuning_save(str(path))
+    text = path.read_text()
+    assert '"segsalsa-tuning-1"' in text and '"precision": "fp64"' in text
+    S.segsalsa_tuning_clear()
+    assert not S.segsalsa_tuning_get(9, 61, 34, 2, 0)[1]
+    # one extra entry that does not fit is skipped, the others are read
+    text = text.replace("\n  ]", ',\n    {"K": 16, "H": 40, "W": 60, "M": 2, "precision": "fp32", "tile_rows": 40, '
+                                 '"tile_cols": 60, "classes_per_wave": 1, "rows_per_block": 0, "row_threads": 0, '
+                                 '"cols_per_block": 0, "col_threads": 0}\n  ]')
+    path.write_text(text)
+    assert S.segsalsa_tuning_load(str(path)) == (2, 1)
+    got, tuned = S.segsalsa_tuning_get(9, 61, 34, 2, 0)
+    assert tuned and (got["tile_rows"], got["tile_cols"], got["classes_per_wave"]) == (8, 17, 1)
+    got, tuned = S.segsalsa_tuning_get(16, 145, 145, 2, 1)
+    assert tuned and got["rows_per_block"] == 2 and got["row_threads"] == 128 and got["us_per_round"] == 99.0
+    with pytest.raises(S.SegsalsaError):
+        S.segsalsa_tuning_load(str(tmp_path / "missing.json"))
+
+
+def test_shipped_cache_is_read(S):
+    """The cache shipped with the package loads without skipped entries, and its shapes plan as tuned."""
+    if not os.path.exists(S.DEFAULT_TUNING_CACHE):
+        pytest.skip("no tuning cache shipped")
+    import json
+    S.segsalsa_tuning_clear()
+    loaded, skipped = S.segsalsa_tuning_load(S.DEFAULT_TUNING_CACHE)
+    entries = json.load(open(S.DEFAULT_TUNING_CACHE))["entries"]
+    assert loaded == len(entries) and skipped == 0
+    for e in entries:
+        got, tuned = S.segsalsa_tuning_get(e["K"], e["H"], e["W"], e["M"], 1 if e["precision"] == "fp64" else 0)
+        assert tuned and got["tile_rows"] == e["tile_rows"] and got["col_threads"] == e["col_threads"]
+
+
+def test_autotune_argument_errors(S):
+    pr = base_problem(S)
+    s = pr.c_struct()
+    n = ctypes.c_size_t(0)
+    assert S.lib().segsalsa_str_autotune_workspace_size(ctypes.byref(s), 0, ctypes.byref(n)) == OK
+    st, plain = status_of_size(S, pr)
+    assert n.value >= plain
+    t = S.segsalsa_tuning()
+    dummy = ctypes.c_void_p(256)
+    assert S.lib().segsalsa_str_autotune(ctypes.byref(s), 0, dummy, dummy, dummy, n.value, 5, ctypes.byref(t),
+                                         None) == INVALID          # z_scratch aliases input
+    assert S.lib().segsalsa_str_autotune(ctypes.byref(s), 0, dummy, ctypes.c_void_p(512), dummy, n.value, 0,
+                                         ctypes.byref(t), None) == INVALID   # rounds out of range

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import FP32_TOL, FP64_TOL, need_gpu, oracle_solve, say
+from gpu_common import check_err, FP32_TOL, FP64_TOL, need_gpu, oracle_many, oracle_solve, rounded_input, say
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -132,8 +132,31 @@ def test_batch_workload_fp32_vs_fp64():
     z32, _, _ = run_batch(S, shapes, probs, c, B["M"], 1.0, lams, mus, B["iters"], torch.float32, graph=True)
     err = max(float(torch.max(torch.abs(a - b.double())).item()) for a, b in zip(z64, z32))
     say(f"  max |z_fp32 - z_fp64| over the batch = {err:.2e}")
-    assert err <= FP32_TOL
+    check_err(err, torch.float32, "max |z_fp32 - z_fp64|")
     # two images of the batch against their own single solves
     for i in (0, len(shapes) - 1):
         zs, _ = run_single(S, probs[i], c, B["M"], 1.0, lams[i], mus[i], B["iters"], torch.float64)
         assert torch.equal(z64[i], zs)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_batch_workload_every_image_against_oracle(dtype):
+    """Every image of the 64-image batch against the FP64 oracle after 2 rounds, element by element
+    (the oracle runs in parallel CPU processes)."""
+    S = need_gpu()
+    B = synth.BATCH
+    shapes = synth.batch_shapes()
+    probs = [t[0] for t in synth.make_batch(shapes)]
+    c = synth.gaussian_patch_multipliers(B["M"], B["patch_sigma"])
+    lams, mus = [B["lam"]] * len(shapes), [B["mu"]] * len(shapes)
+    iters = 2
+    say(f"case batch of {len(shapes)} images {dtype}: {iters} rounds, every image against the oracle")
+    zb, _, _ = run_batch(S, shapes, probs, c, B["M"], 1.0, lams, mus, iters, dtype)
+    cw = np.asarray(c, dtype=np.float32).astype(np.float64) if dtype == torch.float32 else np.asarray(c)
+    jobs = [(rounded_input(x, dtype), cw, B["M"], 1.0, lams[i], mus[i], iters, False) for i, x in enumerate(probs)]
+    say("  oracle running in parallel processes")
+    zo = oracle_many(jobs)
+    errs = [float(np.max(np.abs(a.double().cpu().numpy() - b))) for a, b in zip(zb, zo)]
+    worst = int(np.argmax(errs))
+    say(f"  worst image {worst} {shapes[worst]}: max |z_gpu - z_oracle| = {errs[worst]:.3e}")
+    check_err(max(errs), dtype)

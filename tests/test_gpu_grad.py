@@ -212,12 +212,13 @@ def test_fullsize_fd_and_invariants():
     """256x256, K = 8, 3x3 patch, 50 rounds: FP64 adjoint vs central differences of the GPU forward.
 
     The proximity maps have kinks (the clamp at 0, the singular-value
-    thresholds) and after 50 rounds some iterates sit within ~1e-7 of one
-    (active positivity constraints: min z < 0 by 1e-2), so along some
-    directions a central difference straddles a kink unless h is below that
-    distance; the same happens with the CPU oracle against the exact
-    derivative.  Each directional check therefore takes the best of
-    h in {1e-6, 1e-7, 1e-8} (FP64 rounding costs ~1e-7 relative at 1e-8).
+    thresholds), and after 50 rounds some iterates sit within ~1e-7 of one
+    (active positivity constraints: min z < 0 by 1e-2).  A central difference
+    with step h is exact to O(h^2) only while no iterate crosses a kink
+    within +-h, so the step must stay below that distance: h = 1e-8 for every
+    direction.  Its rounding error is about eps |L| / h ~ 1e-8 relative per
+    evaluation (L ~ 1), amplified by the 50 rounds to at most ~1e-6.  The
+    steps 1e-6 and 1e-7 are logged for comparison only.
     Directions: two random ones and one along the gradient's signs.
     """
     S = need_gpu()
@@ -240,16 +241,18 @@ def test_fullsize_fd_and_invariants():
     say(f"  max |sum_k dL/dlogit_k| / max |dL/dlogit| = {inv:.1e}")
     assert inv <= 1e-10
     rng = np.random.default_rng(11)
-    steps = (1e-6, 1e-7, 1e-8)
+    FD_STEP = 1e-8
 
     def check(name, an, fplus_minus):
-        errs = []
-        for h in steps:
+        out = None
+        for h in (1e-6, 1e-7, FD_STEP):
             fp, fm = fplus_minus(h)
             fd = (fp - fm) / (2 * h)
-            errs.append(abs(an - fd) / abs(an))
-            say(f"  {name}: h {h:.0e} adjoint {an:.10e} fd {fd:.10e} rel {errs[-1]:.1e}")
-        return min(errs)
+            err = abs(an - fd) / abs(an)
+            say(f"  {name}: h {h:.0e} adjoint {an:.10e} fd {fd:.10e} rel {err:.1e}")
+            if h == FD_STEP:
+                out = err
+        return out
 
     worst = 0.0
     dirs = [rng.standard_normal(lg.shape), rng.standard_normal(lg.shape), np.sign(gin) * rng.random(lg.shape)]
@@ -261,10 +264,32 @@ def test_fullsize_fd_and_invariants():
     worst = max(worst, check("weights", float(np.sum(gw * dc)),
                              lambda h: (loss(x, c + h * dc, wl.lam), loss(x, c - h * dc, wl.lam))))
     worst = max(worst, check("lambda", gl, lambda h: (loss(x, c, wl.lam + h), loss(x, c, wl.lam - h))))
-    say(f"  worst (best-step) relative difference {worst:.2e}")
+    say(f"  worst relative difference at h = {FD_STEP:.0e}: {worst:.2e}")
     assert worst <= 1e-5
-    # FP32 adjoint on the same cotangent, reported against FP64
+    # FP32 adjoint on the same cotangent against FP64: observed 2.4e-4 (input), <= 7e-7 (lambda,
+    # weights); the gates sit about 5-10x above
     _, _, gi32, gl32, gw32 = fullsize_adjoint(S, wl, d, torch.float32, gz=gz)
     e_in, e_l, e_w = rel(gi32, gin), abs(gl32 - gl) / abs(gl), rel(gw32, gw)
     say(f"  FP32 vs FP64 adjoint: input {e_in:.2e} lambda {e_l:.2e} weights {e_w:.2e}")
-    assert e_in <= 1e-2 and e_l <= 1e-2 and e_w <= 1e-2
+    assert e_in <= 2e-3 and e_l <= 1e-5 and e_w <= 1e-5
+
+
+def test_autograd_function_with_host_parameters():
+    """SegSalsaSTR with lambda and the patch weights as CPU tensors: their gradients come back on
+    the CPU (in their dtype) and equal those of device parameters."""
+    S = need_gpu()
+    H, W, K, M, iters = 20, 23, 4, 1, 6
+    _, logits, _ = synth.make_image(H, W, K, 41, 1.0, 1.5)
+    c = synth.gaussian_patch_multipliers(M, 1.0)
+    wgt = torch.from_numpy(np.random.default_rng(42).standard_normal((K, H, W))).cuda()
+    grads = {}
+    for dev in ("cpu", "cuda"):
+        x = torch.from_numpy(logits).cuda().requires_grad_(True)
+        lam = torch.tensor(0.9, dtype=torch.float64, device=dev, requires_grad=True)
+        cw = torch.tensor(np.asarray(c), dtype=torch.float32, device=dev, requires_grad=True)
+        z = S.SegSalsaSTR.apply(x, lam, cw, M, 1.0, 1.2, iters, True, 3)
+        torch.sum(wgt * z).backward()
+        assert lam.grad.device.type == dev and cw.grad.device.type == dev and cw.grad.dtype == torch.float32
+        grads[dev] = (x.grad.cpu(), lam.grad.cpu(), cw.grad.cpu())
+    for a, b in zip(grads["cpu"], grads["cuda"]):
+        assert torch.equal(a, b)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import (FP32_TOL, FP64_TOL, MARGIN, gpu_solve, need_gpu, oracle_solve, problem_inputs,
+from gpu_common import (check_err, FP32_TOL, FP64_TOL, MARGIN, gpu_solve, need_gpu, oracle_solve, problem_inputs,
                         rounded_input, say, weights_as_seen)
 import synth
 
@@ -45,7 +45,7 @@ def test_small_grids(H, W, K, M, p, iters, dtype):
     zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
     err = np.max(np.abs(z.double().cpu().numpy() - zo))
     say(f"  max|z_gpu - z_oracle| = {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
@@ -61,7 +61,7 @@ def test_plain_64x64(dtype):
     zg = z.double().cpu().numpy()
     err = np.max(np.abs(zg - zo))
     say(f"  max err {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
     srt = np.sort(zo, axis=0)
     sure = (srt[-1] - srt[-2]) > MARGIN
     assert np.array_equal(np.argmax(zg, axis=0)[sure], np.argmax(zo, axis=0)[sure])
@@ -81,7 +81,7 @@ def test_pines_145_short(p, dtype):
                       wl.lam, wl.mu, iters)
     err = np.max(np.abs(z.double().cpu().numpy() - zo))
     say(f"  max err {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
 
 
 def test_logits_and_asymmetric_weights():
@@ -134,4 +134,4 @@ def test_interface_edges(H, W, K, M, p, iters, only, dtype):
     zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
     err = np.max(np.abs(z.double().cpu().numpy() - zo))
     say(f"  max|z_gpu - z_oracle| = {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import FP32_TOL, FP64_TOL, gpu_solve, need_gpu, oracle_solve, rounded_input, say, weights_as_seen
+from gpu_common import check_err, FP32_TOL, FP64_TOL, gpu_solve, need_gpu, oracle_solve, rounded_input, say, weights_as_seen
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +31,7 @@ def test_large_patch_parity(H, W, K, M, p, iters, dtype):
     zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
     err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
     say(f"  max|z_gpu - z_oracle| = {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
 
 
 def test_patch_size_sweep():

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import FP32_TOL, FP64_TOL, MARGIN, need_gpu, rounded_input, say, weights_as_seen
+from gpu_common import check_err, FP32_TOL, FP64_TOL, MARGIN, need_gpu, rounded_input, say, weights_as_seen
 import synth
 from oracle import segsalsa_ref as R
 
@@ -58,7 +58,7 @@ def test_simplex_g4_small(H, W, K, M, p, iters, dtype):
     gap = float(np.max(np.abs(zo - za)))
     say(f"  max|z_gpu - z_oracle| = {err:.3e} (simplex vs affine reading: {gap:.2e})")
     assert gap > 1e-4, "the case should exercise the simplex projection"
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
 
 
 def test_simplex_g4_residuals_match_oracle():
@@ -110,7 +110,7 @@ def test_simplex_g4_pines_145(dtype):
     zg = z.double().cpu().numpy()
     err = float(np.max(np.abs(zg - zo)))
     say(f"  max err {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
     srt = np.sort(zo, axis=0)
     sure = (srt[-1] - srt[-2]) > MARGIN
     assert np.array_equal(np.argmax(zg, axis=0)[sure], np.argmax(zo, axis=0)[sure])
@@ -138,7 +138,7 @@ def test_general_p_small(H, W, K, M, p, iters, dtype):
     zo = oracle_variant(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
     err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
     say(f"  max|z_gpu - z_oracle| = {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)
 
 
 def test_general_p_residuals_and_objective():
@@ -173,4 +173,4 @@ def test_general_p_pines_145(dtype):
                         wl.mu, iters)
     err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
     say(f"  max err {err:.3e}")
-    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    check_err(err, dtype)

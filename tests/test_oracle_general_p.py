@@ -74,3 +74,63 @@ def test_general_p_round_matches_literal_loop():
     assert np.max(np.abs(z_lit - z_red)) < 1e-8
     z_eig = R.solve(probs, pr, N)
     assert np.max(np.abs(z_eig - z_red)) < 1e-12
+
+
+@pytest.mark.parametrize("p,key", [(1.0, "sum_p1"), (2.0, "sum_p2"), (math.inf, "sum_pinf"), (3.0, "sum_p3"),
+                                   (1.5, "sum_p1_5")])
+def test_schatten_norm_hand_example(p, key):
+    """The per-pixel Schatten-p norm (eq. (6)) on a hand-worked 2x2, K = 2 field, for general p too."""
+    from test_oracle_operators import golden
+    g = golden("snorm_2x2")
+    z = g["z"].reshape(2, 2, 2)
+    pr = R.Problem(np.array([1.0]), 0, p, 1.0, 1.0)
+    nrm = R.schatten_norms(z, pr).reshape(2, 2)
+    assert abs(float(np.sum(nrm)) - float(g[key][0])) < 1e-12
+    if p == 3.0:
+        assert abs(float(nrm[0, 0]) - float(g["n00_p3"][0])) < 1e-13
+        assert abs(float(nrm[1, 1]) - float(g["n00_p3"][0])) < 1e-13
+    if p == 1.5:
+        assert abs(float(nrm[0, 0]) - float(g["n00_p1_5"][0])) < 1e-13
+
+
+def test_objective_hand_example_general_p():
+    """Objective of eq. (7) at a feasible-looking field, p = 3, against its hand-worked value."""
+    from test_oracle_operators import golden
+    g = golden("snorm_2x2")
+    z = 0.05 * g["z"].reshape(2, 2, 2) + 0.25
+    ph = np.full((2, 2, 2), 0.5)
+    pr = R.Problem(np.array([1.0]), 0, 3.0, 0.8, 1.0)
+    assert abs(R.objective(z, ph, pr, project=False) - float(g["objective_p3"][0])) < 1e-12
+
+
+@pytest.mark.parametrize("p", [1.25, 3.0, 4.7])
+def test_objective_matches_dense_evaluation(p):
+    """The oracle's objective equals an independent evaluation (dense J by index arithmetic,
+    LAPACK singular values, the l_p norm written out) at random fields, for general p."""
+    rng = np.random.default_rng(int(10 * p))
+    K, H, W, M = 3, 4, 5, 1
+    c = synth.gaussian_patch_multipliers(M, 1.0)
+    Jm = pinlib.dense_jacobian(H, W, K, c, M)
+    for _ in range(3):
+        z = rng.random((K, H, W))
+        ph = rng.random((K, H, W))
+        ph /= ph.sum(0)
+        pr = R.Problem(c, M, p, 0.7, 1.0)
+        ref = pinlib.objective_dense(z.reshape(-1), ph, Jm, K, H * W, (2 * M + 1) ** 2, 0.7, p)
+        assert abs(R.objective(z, ph, pr, project=False) - ref) < 1e-12 * abs(ref)
+
+
+def test_limit_matches_pdhg_general_p():
+    """p = 3: the ADMM limit objective equals the minimum found by an independently written
+    Chambolle-Pock solver (dual prox through its own l_q-ball projection).  At mu = 5 the
+    iteration is feasible to 1e-9 after 500 rounds (the general-p shrink makes it slow to run)."""
+    probs, _, _ = synth.make_image(5, 5, 3, 33, 1.0, 1.0)
+    ph = probs / probs.sum(0)
+    c = synth.gaussian_patch_multipliers(1, 1.0)
+    pr = R.Problem(c, 1, 3.0, 0.6, 5.0)
+    st, _ = R.solve(probs, pr, 500, return_state=True)
+    z = st.z
+    assert np.max(np.abs(z.sum(0) - 1)) < 1e-8 and z.min() > -1e-8
+    obj = R.objective(z, ph, pr)
+    _, obj_pd = pinlib.pdhg(ph, c, 1, 3.0, 0.6, 3000)
+    assert abs(obj_pd - obj) < 1e-6 * abs(obj)
