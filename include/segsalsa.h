@@ -151,6 +151,30 @@ segsalsa_status segsalsa_str_solve(const segsalsa_problem *prob, segsalsa_precis
                                    const void *input, void *z_out, void *workspace, size_t workspace_bytes,
                                    segsalsa_stats *stats, hipStream_t stream);
 
+/*
+ * segsalsa_str_solve for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  It takes no workspace: the solver state lives in a device
+ * array of SEGSALSA_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends, and the call allocates nothing
+ * (no hipMalloc or hipFree, no graph, no events).  The caller still owns
+ * input and z_out, with the meaning of segsalsa_str_solve.
+ *  - A problem whose workspace (segsalsa_str_workspace_size) is larger than
+ *    the array returns UNSUPPORTED.
+ *  - use_graph, residual_every and tol must be 0 (INVALID_ARG); there are no
+ *    stats.  The launches are plain kernel launches on `stream` and can be
+ *    captured into the caller's own graph.
+ *  - Every call on one GPU uses that GPU's single array and leaves its state
+ *    there; each call initialises the state it needs (unless warm_start).
+ *    Calls that overlap on one GPU (on other streams or threads) race for the
+ *    array and give undefined results.  A warm_start call continues from the
+ *    state of the previous call on that GPU, which must have had the same
+ *    problem and precision.
+ */
+#define SEGSALSA_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+segsalsa_status segsalsa_str_solve_noalloc(const segsalsa_problem *prob, segsalsa_precision precision,
+                                           const void *input, void *z_out, hipStream_t stream);
+
 /* One image of a batch: shape, SALSA parameters, and element offsets of its
  * [K][H][W] input and output inside the packed batch buffers. */
 typedef struct {

@@ -20,6 +20,11 @@
 
 using namespace segsalsa;
 
+// Workspace of segsalsa_str_solve_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address on the current GPU comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[SEGSALSA_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -563,11 +568,16 @@ hipEvent_t prof_event_locked() {
   return e;
 }
 
+// Set while segsalsa_str_solve_noalloc runs on this thread: no event records
+// (creating events may allocate).
+thread_local bool g_no_alloc = false;
+
 struct PhaseTimer {
   int phase;
   hipStream_t st;
   hipEvent_t a = nullptr;
   PhaseTimer(int ph, hipStream_t s) : phase(ph), st(s) {
+    if (g_no_alloc) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     if (!g_prof.on) return;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -1660,6 +1670,33 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
   return SEGSALSA_OK;
 }
 
+// Device address of `scratch` on the current GPU, looked up once per device
+// (with that device current) and kept.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
+
+segsalsa_status noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SEGSALSA_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SEGSALSA_OK;
+}
+
+struct NoAllocScope {
+  NoAllocScope() { g_no_alloc = true; }
+  ~NoAllocScope() { g_no_alloc = false; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -1708,6 +1745,33 @@ segsalsa_status segsalsa_str_solve(const segsalsa_problem* prob, segsalsa_precis
   const void* ins[1] = {input};
   return b.c.fp64 ? solve_batch_t<double>(b, workspace, zs, ins, stream, stats)
                   : solve_batch_t<float>(b, workspace, zs, ins, stream, stats);
+}
+
+segsalsa_status segsalsa_str_solve_noalloc(const segsalsa_problem* prob, segsalsa_precision precision,
+                                           const void* input, void* z_out, hipStream_t stream) {
+  g_last_error.clear();
+  Batch b;
+  segsalsa_status s = single_batch(prob, precision, b);
+  if (s != SEGSALSA_OK) return s;
+  if (prob->use_graph) return fail(SEGSALSA_ERR_INVALID_ARG, "the no-allocation entry point launches directly (use_graph = 0)");
+  if (prob->residual_every > 0 || prob->tol > 0.0)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "the no-allocation entry point runs fixed rounds (residual_every = tol = 0)");
+  if (b.total > (size_t)SEGSALSA_NOALLOC_SCRATCH_BYTES)
+    return fail(SEGSALSA_ERR_UNSUPPORTED, "the problem needs %zu bytes of workspace, the no-allocation scratch holds %zu",
+                b.total, (size_t)SEGSALSA_NOALLOC_SCRATCH_BYTES);
+  const size_t ts = b.c.ts;
+  if (!z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "z_out is NULL");
+  if (!prob->warm_start && !input) return fail(SEGSALSA_ERR_INVALID_ARG, "input is NULL");
+  if (input && input == z_out) return fail(SEGSALSA_ERR_INVALID_ARG, "z_out aliases input");
+  if (reinterpret_cast<uintptr_t>(z_out) % ts || reinterpret_cast<uintptr_t>(input) % ts)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "input/z_out not aligned to the element size");
+  void* ws = nullptr;
+  if ((s = noalloc_scratch(&ws)) != SEGSALSA_OK) return s;
+  NoAllocScope scope;
+  void* zs[1] = {z_out};
+  const void* ins[1] = {input};
+  return b.c.fp64 ? solve_batch_t<double>(b, ws, zs, ins, stream, nullptr)
+                  : solve_batch_t<float>(b, ws, zs, ins, stream, nullptr);
 }
 
 static segsalsa_status batch_common(int32_t n, const segsalsa_image* imgs, const segsalsa_batch_params* bp,

@@ -133,6 +133,8 @@ def lib():
     L.segsalsa_str_autotune.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
                                         c_int32, POINTER(segsalsa_tuning), c_void_p]
     L.segsalsa_str_autotune.restype = c_int32
+    L.segsalsa_str_solve_noalloc.argtypes = [POINTER(segsalsa_problem), c_int32, c_void_p, c_void_p, c_void_p]
+    L.segsalsa_str_solve_noalloc.restype = c_int32
     _lib = L
     if os.path.exists(DEFAULT_TUNING_CACHE) and not os.environ.get("SEGSALSA_NO_TUNING_CACHE"):
         segsalsa_tuning_load(DEFAULT_TUNING_CACHE)
@@ -219,6 +221,19 @@ def segsalsa_str_solve(problem: Problem, inp, z_out, workspace, stats: bool = Fa
         return None
     return dict(primal_res=st.primal_res, dual_res=st.dual_res, objective=st.objective,
                 rounds_done=st.rounds_done, flags=st.flags)
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # SEGSALSA_NOALLOC_SCRATCH_BYTES
+
+
+def segsalsa_str_solve_noalloc(problem: Problem, inp, z_out, stream=None):
+    """segsalsa_str_solve without a workspace: the state lives in the library's per-GPU scratch array."""
+    prec = _prec(z_out.dtype)
+    nel = problem.K * problem.H * problem.W
+    s = problem.c_struct()
+    pin = _dev_ptr(inp, "input", z_out.dtype, nel) if inp is not None else None
+    _check(lib().segsalsa_str_solve_noalloc(ctypes.byref(s), prec, pin, _dev_ptr(z_out, "z_out", None, nel),
+                                            _stream(stream)))
 
 
 def segsalsa_str_labels(z, labels, stream=None):
