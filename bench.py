@@ -327,6 +327,10 @@ def main():
                     help="time only the differentiable solve (forward with checkpoints + reverse sweep)")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of one graph")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on every workload shape (the 64 batch images included) in FP32 and "
+                         "FP64 and write the package's tuning cache")
+    ap.add_argument("--tune-rounds", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 512 MiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -355,6 +359,17 @@ def main():
 
     if args.sweep:
         print(json.dumps(bench_sweep(S, torch, synth, args.workload, steps=args.steps)), flush=True)
+        return
+
+    if args.tune:
+        from paper_1504_07028_amd import autotune
+        shapes = [(w.K, w.H, w.W, w.M) for w in synth.WORKLOADS.values()]
+        shapes += sorted({(K, H, W, synth.BATCH["M"]) for (H, W, K) in synth.batch_shapes()})
+        t0 = time.perf_counter()
+        res = autotune.tune_shapes(shapes, ["fp32", "fp64"], args.tune_rounds, S.DEFAULT_TUNING_CACHE, fresh=True,
+                                   log=log)
+        print(json.dumps({"tuned": len(res), "seconds": time.perf_counter() - t0,
+                          "cache": os.path.relpath(S.DEFAULT_TUNING_CACHE, ROOT)}), flush=True)
         return
 
     if args.adjoint_only:

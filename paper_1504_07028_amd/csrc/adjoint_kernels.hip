@@ -50,7 +50,8 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z before the round
   T* rt = zt + K * plane;              // [K][ER][EC] rb = A^{-1} zb'
   T* acc = rt + K * plane;             // [K][ER][EC] partial sums of zb
-  T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
+  // offsets from smem (not integer casts of pointers) keep these accesses LDS instructions
+  T* part = reinterpret_cast<T*>(smem + (((size_t)3 * K * plane * sizeof(T) + 15) & ~size_t(15)));
   // [NS][64] FP64 per-pixel class sums and [10][64] FP64 per-pixel coefficients
   double* tot = reinterpret_cast<double*>(part + 2 * NS * nw * 64);
   double* coef = tot + NS * 64;

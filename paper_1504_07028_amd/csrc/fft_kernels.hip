@@ -24,6 +24,26 @@
 
 namespace segsalsa {
 
+// Every LDS buffer and table below is passed with its address space spelled
+// out (lptr: LDS, gptr: global): generic pointers would become FLAT
+// instructions, which are slower and make every LDS wait also wait for the
+// outstanding global loads.
+template <typename T>
+using lptr = __attribute__((address_space(3))) T*;
+
+// Complex element loads and stores through those pointers, member by member
+// (the implicit copy operations of C2 only bind to generic addresses).
+template <typename P>
+__device__ __forceinline__ auto ldc(P p) {
+  using T = decltype(+p->x);
+  return C2<T>{p->x, p->y};
+}
+template <typename P, typename V>
+__device__ __forceinline__ void stc(P p, const V& v) {
+  p->x = v.x;
+  p->y = v.y;
+}
+
 template <typename T>
 __device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -131,7 +151,7 @@ struct Bfly<T, 8> {
 // (entry m N / P = exp(-2 pi i m / P)); the index is wavefront-uniform.
 template <typename T, int P>
 struct BflyOdd {
-  __device__ __forceinline__ static void run(C2<T>* v, T sg, const C2<T>* __restrict__ gtw, int stride) {
+  __device__ __forceinline__ static void run(C2<T>* v, T sg, gptr<const C2<T>> gtw, int stride) {
     constexpr int Hh = (P - 1) / 2;
     C2<T> sm[Hh], df[Hh];
     C2<T> y0 = v[0];
@@ -146,7 +166,7 @@ struct BflyOdd {
       C2<T> a = v[0], b = {T(0), T(0)};
 #pragma unroll
       for (int r = 1; r <= Hh; ++r) {
-        const C2<T> w = gtw[((r * q) % P) * stride];
+        const C2<T> w = ldc(gtw + ((r * q) % P) * stride);
         const T c = w.x, sn = -w.y;
         a.x += sm[r - 1].x * c;
         a.y += sm[r - 1].y * c;
@@ -172,8 +192,8 @@ __host__ __device__ constexpr bool is_odd_prime_radix(int R) {
 // One Stockham stage with a register butterfly of radix R, in place in LDS.
 // nb transforms of length N; element i of transform b sits at b*bs + i*es.
 // Ns is the product of the radices of the previous stages.
-template <typename T, int R, int EPT>
-__device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int bs, const C2<T>* tw, const C2<T>* gtw, int Ns,
+template <typename T, int R, int EPT, typename TW>
+__device__ __forceinline__ void stage_reg(lptr<C2<T>> buf, int N, int nb, int es, int bs, TW tw, gptr<const C2<T>> gtw, int Ns,
                           bool inv) {
   constexpr int IT = (EPT + R - 1) / R;
   const T sg = inv ? T(1) : T(-1);
@@ -200,10 +220,10 @@ __device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int
       const int k = j % Ns;
       const int base = b * bs;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[base + (j + r * NR) * es];
+      for (int r = 0; r < R; ++r) v[it][r] = ldc(buf + base + (j + r * NR) * es);
       if (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[it][r] = twmul(v[it][r], tw[k * r * stw], inv);
+        for (int r = 1; r < R; ++r) v[it][r] = twmul(v[it][r], ldc(tw + k * r * stw), inv);
       }
       if constexpr (is_odd_prime_radix<T>(R))
         BflyOdd<T, R>::run(v[it], sg, gtw, N / R);
@@ -217,7 +237,7 @@ __device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int
   for (int it = 0; it < IT; ++it) {
     if (ob[it] >= 0) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[ob[it] + r * Ns * es] = v[it][r];
+      for (int r = 0; r < R; ++r) stc(buf + ob[it] + r * Ns * es, v[it][r]);
     }
   }
   __syncthreads();
@@ -233,8 +253,8 @@ __device__ __forceinline__ void stage_reg(C2<T>* buf, int N, int nb, int es, int
 //   x_r w + x_(R-r) conj(w) = (x_r + x_(R-r)) Re w + i Im w (x_r - x_(R-r)),
 // and output R - q takes conj(w) in place of w, which halves the complex
 // multiplies and the LDS reads.
-template <typename T, int EPT>
-__device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, int es, int bs, const C2<T>* tw,
+template <typename T, int EPT, typename TW>
+__device__ __forceinline__ void stage_generic(lptr<C2<T>> buf, int N, int R, int nb, int es, int bs, TW tw,
                               int Ns, bool inv) {
   const int NR = N / R;
   const int total = nb * N;
@@ -253,7 +273,7 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
       const int k = j % Ns;
       if (r > 0 && k > 0) {
         const int idx = b * bs + rem * es;
-        buf[idx] = twmul(buf[idx], tw[r * k * stw], inv);   // r k stw < R Ns stw = N
+        stc(buf + idx, twmul(ldc(buf + idx), ldc(tw + r * k * stw), inv));   // r k stw < R Ns stw = N
       }
     }
     __syncthreads();
@@ -285,16 +305,16 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
       }
       const int j = rem / H1, q = rem - j * H1;
       const int k = j % Ns;
-      const C2<T>* xj = buf + b * bs + j * es;
+      const lptr<C2<T>> xj = buf + b * bs + j * es;
       const int sr = NR * es;
-      const C2<T> x0 = xj[0];
+      const C2<T> x0 = ldc(xj);
       C2<T> s = x0, t = x0;   // outputs q and R - q
       int m = 0;
       for (int r = 1; r <= half; ++r) {
         m += q;
         if (m >= R) m -= R;
-        const C2<T> xa = xj[r * sr], xb = xj[(R - r) * sr];
-        const C2<T> w = tw[m * NR];
+        const C2<T> xa = ldc(xj + r * sr), xb = ldc(xj + (R - r) * sr);
+        const C2<T> w = ldc(tw + m * NR);
         const T wi = inv ? -w.y : w.y;
         const T pr = xa.x + xb.x, pi = xa.y + xb.y, dr = xa.x - xb.x, di = xa.y - xb.y;
         s.x += pr * w.x - wi * di;
@@ -314,8 +334,8 @@ __device__ __forceinline__ void stage_generic(C2<T>* buf, int N, int R, int nb, 
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < EPTP; ++it) {
-    if (ia[it] >= 0) buf[ia[it]] = oa[it];
-    if (ib[it] >= 0) buf[ib[it]] = ob[it];
+    if (ia[it] >= 0) stc(buf + ia[it], oa[it]);
+    if (ib[it] >= 0) stc(buf + ib[it], ob[it]);
   }
   __syncthreads();
 }
@@ -325,10 +345,11 @@ __device__ inline C2<T> cmul(C2<T> a, C2<T> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
+
 // Mixed-radix Stockham DFT over the given factors (unnormalised).
-template <typename T, int EPT>
-__device__ __forceinline__ void stockham(C2<T>* buf, int N, int nst, const int* rad, int nb, int es, int bs, const C2<T>* tw,
-                         const C2<T>* gtw, bool inv) {
+template <typename T, int EPT, typename TW>
+__device__ __forceinline__ void stockham(lptr<C2<T>> buf, int N, int nst, const int* rad, int nb, int es, int bs, TW tw,
+                         gptr<const C2<T>> gtw, bool inv) {
   int Ns = 1;
   for (int s = 0; s < nst; ++s) {
     const int R = rad[s];
@@ -336,9 +357,9 @@ __device__ __forceinline__ void stockham(C2<T>* buf, int N, int nst, const int* 
 #define SEG_STAGE(RR)                                                                     \
   case RR:                                                                                \
     if constexpr (RR <= 8 || is_odd_prime_radix<T>(RR))                                   \
-      stage_reg<T, RR, EPT>(buf, N, nb, es, bs, tw, gtw, Ns, inv);                        \
+      stage_reg<T, RR, EPT, TW>(buf, N, nb, es, bs, tw, gtw, Ns, inv);                    \
     else                                                                                  \
-      stage_generic<T, EPT>(buf, N, RR, nb, es, bs, tw, Ns, inv);                         \
+      stage_generic<T, EPT, TW>(buf, N, RR, nb, es, bs, tw, Ns, inv);                     \
     break;
       SEG_STAGE(2)
       SEG_STAGE(3)
@@ -349,7 +370,7 @@ __device__ __forceinline__ void stockham(C2<T>* buf, int N, int nst, const int* 
       SEG_STAGE(11)
       SEG_STAGE(13)
 #undef SEG_STAGE
-      default: stage_generic<T, EPT>(buf, N, R, nb, es, bs, tw, Ns, inv); break;
+      default: stage_generic<T, EPT, TW>(buf, N, R, nb, es, bs, tw, Ns, inv); break;
     }
     Ns *= R;
   }
@@ -363,10 +384,10 @@ __device__ __forceinline__ void stockham(C2<T>* buf, int N, int nst, const int* 
 // nb * M elements of LDS scratch.  The workgroup must hold at least
 // nb * max(N, M) / EPT threads.
 template <typename T, int EPT>
-__device__ __forceinline__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb, int es, int bs, const C2<T>* tw,
-                        const FftTab<T>& tab, C2<T>* scr, bool inv) {
+__device__ __forceinline__ void fft_lds(lptr<C2<T>> buf, const FftPlanDev& p, int nb, int es, int bs,
+                                        lptr<const C2<T>> tw, const FftTab<T>& tab, lptr<C2<T>> scr, bool inv) {
   if (!p.blu) {
-    stockham<T, EPT>(buf, p.N, p.nst, p.rad, nb, es, bs, tw, tab.tw, inv);
+    stockham<T, EPT>(buf, p.N, p.nst, p.rad, nb, es, bs, tw, glob(tab.tw), inv);
     return;
   }
   const int N = p.N, M = p.M;
@@ -374,33 +395,33 @@ __device__ __forceinline__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb,
     const int b = idx / M, n = idx - b * M;
     C2<T> v = {T(0), T(0)};
     if (n < N) {
-      C2<T> c = tab.chirp[n];
+      C2<T> c = ldc(glob(tab.chirp) + n);
       if (inv) c.y = -c.y;
-      v = cmul(buf[b * bs + n * es], c);
+      v = cmul(ldc(buf + b * bs + n * es), c);
     }
-    scr[idx] = v;
+    stc(scr + idx, v);
   }
   __syncthreads();
-  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, tab.twM, false);
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, glob(tab.twM), glob(tab.twM), false);
   for (int idx = threadIdx.x; idx < nb * M; idx += blockDim.x) {
     const int m = idx & (M - 1);
     C2<T> w;
     if (inv) {  // DFT of conj(d) is conj(DFT(d)) read at -m
-      w = tab.bf[(M - m) & (M - 1)];
+      w = ldc(glob(tab.bf) + ((M - m) & (M - 1)));
       w.y = -w.y;
     } else {
-      w = tab.bf[m];
+      w = ldc(glob(tab.bf) + m);
     }
-    scr[idx] = cmul(scr[idx], w);
+    stc(scr + idx, cmul(ldc(scr + idx), w));
   }
   __syncthreads();
-  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, tab.twM, tab.twM, true);
+  stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, glob(tab.twM), glob(tab.twM), true);
   const T invM = T(1) / T(M);
   for (int idx = threadIdx.x; idx < nb * N; idx += blockDim.x) {
     const int b = idx / N, k = idx - b * N;
-    C2<T> c = tab.chirp[k];
+    C2<T> c = ldc(glob(tab.chirp) + k);
     if (inv) c.y = -c.y;
-    buf[b * bs + k * es] = cscale(cmul(scr[b * M + k], c), invM);
+    stc(buf + b * bs + k * es, cscale(cmul(ldc(scr + b * M + k), c), invM));
   }
   __syncthreads();
 }
@@ -410,20 +431,20 @@ __device__ __forceinline__ void fft_lds(C2<T>* buf, const FftPlanDev& p, int nb,
 template <typename T>
 __global__ void __launch_bounds__(kFftMaxThreads) bluestein_table_kernel(FftPlanDev p, FftTab<T> tab, C2<T>* bf_out) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  lptr<C2<T>> buf = (lptr<C2<T>>)smem;
   const int N = p.N, M = p.M;
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
     C2<T> v = {T(0), T(0)};
     const int j = m < N ? m : (M - m < N ? M - m : -1);
     if (j >= 0) {
-      v = tab.chirp[j];
+      v = ldc(glob(tab.chirp) + j);
       v.y = -v.y;
     }
-    buf[m] = v;
+    stc(buf + m, v);
   }
   __syncthreads();
-  stockham<T, kFftEptMax>(buf, M, p.mnst, p.mrad, 1, 1, M, tab.twM, tab.twM, false);
-  for (int m = threadIdx.x; m < M; m += blockDim.x) bf_out[m] = buf[m];
+  stockham<T, kFftEptMax>(buf, M, p.mnst, p.mrad, 1, 1, M, glob(tab.twM), glob(tab.twM), false);
+  for (int m = threadIdx.x; m < M; m += blockDim.x) bf_out[m] = ldc(buf + m);
 }
 
 template <typename T>
@@ -450,7 +471,7 @@ hipError_t launch_bluestein_table(const FftPlanDev& p, const FftTab<double>& tab
 template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  lptr<C2<T>> buf = (lptr<C2<T>>)smem;
   const int blk = xcd_block();   // consecutive rows (neighbouring grown-tile rows) on one XCD
   const RowFwdArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
   const int bid = blk - a.block0;
@@ -460,9 +481,12 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
-  C2<T>* tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
+  lptr<C2<T>> tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
+  const FftTab<T>& tab = a.tab;
   if (!a.plan.blu)
-    for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tab.tw[t];
+    for (int t = threadIdx.x; t < W; t += blockDim.x) stc(tw + t, ldc(glob(tab.tw) + t));
+  const gptr<const T> acc = glob(a.acc);
+  const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   // right-hand side = sum of the grown-tile partial sums covering (r, c)
   const size_t plane = (size_t)a.g.ER * a.g.EC;
   const bool has1 = k1 < a.K;
@@ -476,8 +500,8 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < nb * W) {
       const int rr = idx / W, c = idx - rr * W;
-      const int* rl = a.frow + (row0 + rr);   // [kFoldStride][H]
-      const int* cl = a.fcol + c;             // [kFoldStride][W]
+      const gptr<const int> rl = frow + (row0 + rr);   // [kFoldStride][H]
+      const gptr<const int> cl = fcol + c;             // [kFoldStride][W]
       const int nr = rl[0], nc = cl[0];
       const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[W], c1e = cl[2 * W];
       T s0 = T(0), s1 = T(0);
@@ -488,23 +512,23 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
           const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[(size_t)(1 + j) * W]);
           const size_t tile = (size_t)tr * a.g.ntc + (cj >> kFoldShift);
           const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & kFoldMask);
-          s0 += a.acc[off];
-          if (has1) s1 += a.acc[off + plane];
+          s0 += acc[off];
+          if (has1) s1 += acc[off + plane];
         }
       }
-      buf[idx] = C2<T>{s0, s1};
+      stc(buf + idx, C2<T>{s0, s1});
     }
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, false);
-  C2<T>* out = a.spec + ((size_t)m * H + row0) * W;
-  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) out[idx] = buf[idx];
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, tab, tw, false);
+  const gptr<C2<T>> out = glob(a.spec) + ((size_t)m * H + row0) * W;
+  for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) stc(out + idx, ldc(buf + idx));
 }
 
 template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  lptr<C2<T>> buf = (lptr<C2<T>>)smem;
   const int blk = xcd_block();   // adjacent column blocks (shared cache lines) on one XCD
   const ColArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
   const int bid = blk - a.block0;
@@ -514,38 +538,40 @@ __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __rest
   const int m = bid / ncb;
   const int col0 = (bid - m * ncb) * CB;
   const int nb = min(CB, W - col0);
-  C2<T>* sp = a.spec + (size_t)m * H * W + col0;
-  C2<T>* tw = buf + CB * H;  // twiddles, or Bluestein scratch
+  const gptr<C2<T>> sp = glob(a.spec) + (size_t)m * H * W + col0;
+  const FftTab<T>& tab = a.tab;
+  lptr<C2<T>> tw = buf + CB * H;  // twiddles, or Bluestein scratch
   if (!a.plan.blu)
-    for (int t = threadIdx.x; t < H; t += blockDim.x) tw[t] = a.tab.tw[t];
+    for (int t = threadIdx.x; t < H; t += blockDim.x) stc(tw + t, ldc(glob(tab.tw) + t));
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {  // blockDim.x * EPT >= H * nb: loads in flight together
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < H * nb) {
       const int y = idx / nb, j = idx - y * nb;
-      buf[idx] = sp[(size_t)y * W + j];
+      stc(buf + idx, ldc(sp + (size_t)y * W + j));
     }
   }
   __syncthreads();
   // forward column DFT, division by the symbol, inverse column DFT
-  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, a.tab, tw, false);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, tab, tw, false);
+  const gptr<const double> sx = glob(a.sx), sy = glob(a.sy);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
-    const T inv = T(a.scale) / (T(3) + T(a.wsum) * T(a.sx[col0 + j] + a.sy[y]));
-    buf[idx] = cscale(buf[idx], inv);
+    const T inv = T(a.scale) / (T(3) + T(a.wsum) * T(sx[col0 + j] + sy[y]));
+    stc(buf + idx, cscale(ldc(buf + idx), inv));
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, a.tab, tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, tab, tw, true);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
     const int y = idx / nb, j = idx - y * nb;
-    sp[(size_t)y * W + j] = buf[idx];
+    stc(sp + (size_t)y * W + j, ldc(buf + idx));
   }
 }
 
 template <typename T, int EPT, int MAXT>
 __global__ void __launch_bounds__(MAXT) fft_rows_inv_kernel(const RowInvArgs<T>* __restrict__ descs, int ndesc) {
   extern __shared__ __align__(16) unsigned char smem[];
-  C2<T>* buf = reinterpret_cast<C2<T>*>(smem);
+  lptr<C2<T>> buf = (lptr<C2<T>>)smem;
   const int blk = xcd_block();
   const RowInvArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
   const int bid = blk - a.block0;
@@ -554,23 +580,24 @@ __global__ void __launch_bounds__(MAXT) fft_rows_inv_kernel(const RowInvArgs<T>*
   const int m = bid / nrb;
   const int row0 = (bid - m * nrb) * a.rows_per_block;
   const int nb = min(a.rows_per_block, H - row0);
-  const C2<T>* in = a.spec + ((size_t)m * H + row0) * W;
-  C2<T>* tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
+  const gptr<const C2<T>> in = glob(a.spec) + ((size_t)m * H + row0) * W;
+  const FftTab<T>& tab = a.tab;
+  lptr<C2<T>> tw = buf + a.rows_per_block * W;  // twiddles, or Bluestein scratch
   if (!a.plan.blu)
-    for (int t = threadIdx.x; t < W; t += blockDim.x) tw[t] = a.tab.tw[t];
+    for (int t = threadIdx.x; t < W; t += blockDim.x) stc(tw + t, ldc(glob(tab.tw) + t));
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {  // blockDim.x * EPT >= nb * W: loads in flight together
     const int idx = threadIdx.x + it * blockDim.x;
-    if (idx < nb * W) buf[idx] = in[idx];
+    if (idx < nb * W) stc(buf + idx, ldc(in + idx));
   }
   __syncthreads();
-  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, a.tab, tw, true);
+  fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, tab, tw, true);
   const int k0 = 2 * m, k1 = 2 * m + 1;
-  T* z0 = a.z + ((size_t)k0 * H + row0) * W;
-  T* z1 = a.z + ((size_t)k1 * H + row0) * W;
+  const gptr<T> z0 = glob(a.z) + ((size_t)k0 * H + row0) * W;
+  const gptr<T> z1 = glob(a.z) + ((size_t)k1 * H + row0) * W;
   const bool has1 = k1 < a.K;
   for (int idx = threadIdx.x; idx < nb * W; idx += blockDim.x) {
-    const C2<T> v = buf[idx];
+    const C2<T> v = ldc(buf + idx);
     z0[idx] = v.x;
     if (has1) z1[idx] = v.y;
   }

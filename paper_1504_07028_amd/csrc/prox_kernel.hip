@@ -60,7 +60,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   // [2][6][nw][64] per-class partial sums, 16-byte aligned (also read as doubles);
   // with g4s, after the FP64 sums and coefficients, [2][K][64] v4 of every
   // class (double-buffered by step like the sums)
-  T* part = reinterpret_cast<T*>((reinterpret_cast<uintptr_t>(acc + K * plane) + 15) & ~uintptr_t(15));
+  // (offsets from smem, not integer casts of pointers: the compiler then keeps
+  // these accesses as LDS instructions instead of generic FLAT ones, which
+  // would also wait for outstanding global memory operations)
+  T* part = reinterpret_cast<T*>(smem + (((size_t)2 * K * plane * sizeof(T) + 15) & ~size_t(15)));
   // [6][64] FP64 per-pixel class sums and [5][64] FP64 per-pixel coefficients
   double* tot = reinterpret_cast<double*>(part + 2 * 6 * nw * 64);
   double* coef = tot + 6 * 64;

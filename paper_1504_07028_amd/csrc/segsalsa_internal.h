@@ -127,13 +127,22 @@ __host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, 
 // (workgroup i runs on XCD i mod 8), and each XCD has its own L2.  Kernels
 // whose neighbouring work items share cache lines (the halos of adjacent
 // tiles, the adjacent column blocks of one row) renumber their workgroups so
-// that each XCD gets one contiguous range of work items.
+// that each XCD gets runs of kXcdRun consecutive work items: in every group
+// of 8 kXcdRun workgroups, XCD x takes items x kXcdRun .. x kXcdRun + kXcdRun - 1
+// (the last, partial group is split into eight near-equal runs).  Short runs
+// keep the XCDs balanced when the work items of a launch differ in cost (the
+// images of a batch).
 constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
 __device__ inline int xcd_block() {
   const int n = gridDim.x, i = blockIdx.x;
-  const int q = n / kXcds, r = n - q * kXcds;
-  const int x = i % kXcds, j = i / kXcds;
-  return x * q + (x < r ? x : r) + j;
+  const int G = kXcds * kXcdRun;
+  const int g = i / G, full = n / G;
+  const int x = i % kXcds;
+  if (g < full) return g * G + x * kXcdRun + (i - g * G) / kXcds;
+  const int m = n - full * G, base = full * G;   // the partial group
+  const int q = m / kXcds, r = m - q * kXcds, j = (i - base) / kXcds;
+  return base + x * q + (x < r ? x : r) + j;
 }
 
 // Per-pixel arithmetic parameters of one round.
