@@ -301,6 +301,12 @@ segsalsa_status segsalsa_str_backward(const segsalsa_problem *prob, segsalsa_pre
 typedef struct {
   int32_t tile_rows, tile_cols;  /* prox tile in pixels (both > 0), or 0 for the planner's            */
   int32_t classes_per_wave;      /* classes per wavefront of the prox kernel: 1, 2 or 4, or 0          */
+  int32_t prefetch;              /* 1: the prox kernel build that loads step s + 1 while step s
+                                    updates (FP32, classes_per_wave = 2, patch radius <= 2); 0: not    */
+  int32_t generic_fft;           /* 1: the general mixed-radix FFT kernels also for power-of-two sides
+                                    (64 .. 4096), which otherwise take the fixed-structure kernels with
+                                    N / 16 threads per transform (their threads are then rows or
+                                    columns per block times N / 16)                                    */
   int32_t rows_per_block;        /* rows per workgroup of the row DFT passes (> 0), or 0               */
   int32_t row_threads;           /* threads per row workgroup, a multiple of 64 in [64, 1024], or 0    */
   int32_t cols_per_block;        /* columns per workgroup of the column pass (> 0), or 0               */

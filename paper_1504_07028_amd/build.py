@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsegsalsa.so")
-SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "misc_kernels.hip", "residual_kernels.hip", "adjoint_kernels.hip"]
+SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "fft_pow2_kernels.hip", "misc_kernels.hip",
+           "residual_kernels.hip", "adjoint_kernels.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -37,7 +38,7 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libsegsalsa.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

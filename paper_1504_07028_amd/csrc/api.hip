@@ -105,6 +105,7 @@ struct Plan {
   int K, H, W, M, L, P;
   TileGeom g;
   int nw, kpw;   // prox workgroup: wavefronts and classes per wavefront
+  bool pf;       // the prefetching build of the prox kernel
   size_t prox_lds;
   int anw, akpw;  // adjoint workgroup (differentiable solves only)
   int g4s;        // simplex g4: the prox kernel stages v4 of all classes in LDS
@@ -112,6 +113,7 @@ struct Plan {
   FftPlanDev frow, fcol;
   // FFT workgroups: transforms per workgroup, threads, elements per thread
   int rows_per_block, row_threads, row_ept;
+  int row_p2, col_p2;   // power-of-two length of the fixed-structure row (column) kernels, 0: general kernels
   size_t row_lds;
   int cols_per_block, col_threads, col_ept;
   size_t col_lds;
@@ -168,7 +170,7 @@ std::vector<TileGeom> tile_candidates(const Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
   // resident workgroups per CU allowed by the register budget of the chosen instantiation
-  const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw) / 256);
+  const int waves_per_simd = std::max(1, prox_max_threads_rt(p.fp64, p.M, p.kpw, p.pf) / 256);
   const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
   struct Cand {
     TileGeom g;
@@ -345,10 +347,14 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   // prox workgroup: the tuned classes per wavefront, else the fewest whose
   // register budget allows ceil(K/kpw) wavefronts
   p.kpw = 0;
+  p.pf = tn.prefetch != 0;
+  if (p.pf && (tn.classes_per_wave != 2 || !prox_has_prefetch_rt(p.fp64, p.M, 2)))
+    return fail(SEGSALSA_ERR_UNSUPPORTED, "the prefetching prox kernel is built for FP32, 2 classes per wavefront, "
+                "patch radius <= 2");
   for (int kpw : {1, 2, 4}) {
     if (tn.classes_per_wave > 0 && kpw != tn.classes_per_wave) continue;
     const int nw = ceil_div(K, kpw);
-    if (nw <= 16 && nw * 64 <= prox_max_threads_rt(p.fp64, p.M, kpw)) {
+    if (nw <= 16 && nw * 64 <= prox_max_threads_rt(p.fp64, p.M, kpw, p.pf)) {
       p.kpw = kpw;
       p.nw = nw;
       break;
@@ -401,7 +407,31 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   // has the rows.  Columns: blocks of adjacent columns so that each row of
   // a block is one contiguous run, at most 80 KB of LDS (two workgroups per
   // compute unit) and at least one workgroup per compute unit.
-  {
+  // Power-of-two lengths 64 .. 4096 (without Bluestein) take the kernels
+  // whose transform structure is fixed at compile time: N / 16 threads per
+  // transform, about 256 threads per row workgroup and 512 per column
+  // workgroup (FP64: 256), each transform in its own padded LDS region.
+  const int maxthr_p2 = p.fp64 ? kFftNarrowThreads : kFftMaxThreads;
+  p.row_p2 = !p.frow.blu && p2_length(W) && !tn.generic_fft ? W : 0;
+  p.col_p2 = !p.fcol.blu && p2_length(H) && !tn.generic_fft ? H : 0;
+  if (p.row_p2) {
+    const int tpt = W / 16;
+    // default: about 256 threads, at least one wavefront, and two workgroups per CU when the image has the rows
+    long long rpb = tn.rows_per_block > 0
+                        ? std::min<long long>(tn.rows_per_block, H)
+                        : std::min<long long>(H, std::max<long long>(std::max(1, 64 / tpt),
+                                                                     std::min<long long>(256 / tpt, (long long)p.P * H /
+                                                                                                        (2 * kTargetGroups))));
+    const long long thr = rpb * tpt;
+    const size_t lds = (size_t)rpb * p2_region(W) * cs;
+    if (thr > maxthr_p2 || lds > kLdsBudget || (tn.row_threads > 0 && tn.row_threads != thr))
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld rows of %d per workgroup (%lld threads, %zu bytes of LDS) do not fit",
+                  rpb, W, thr, lds);
+    p.rows_per_block = (int)rpb;
+    p.row_threads = (int)thr;
+    p.row_ept = 0;
+    p.row_lds = lds;
+  } else {
     const int Lr = p.frow.blu ? p.frow.M : W;      // elements per row inside the transform
     auto lds_of = [&](long long rpb) {
       return ((size_t)rpb * W + (p.frow.blu ? (size_t)rpb * Lr : (size_t)W)) * cs;
@@ -432,7 +462,25 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     p.row_ept = ept;
     p.row_lds = lds_of(rpb);
   }
-  {
+  if (p.col_p2) {
+    const int tpt = H / 16;
+    // default: about 512 threads (FP64: 256), at least one wavefront, one workgroup per CU when there are the columns
+    long long cb = tn.cols_per_block > 0
+                       ? std::min<long long>(tn.cols_per_block, W)
+                       : std::min<long long>(W, std::max<long long>(std::max(1, 64 / tpt),
+                                                                    std::min<long long>((p.fp64 ? 256 : 512) / tpt,
+                                                                                        (long long)p.P * W /
+                                                                                            kTargetGroups)));
+    const long long thr = cb * tpt;
+    const size_t lds = (size_t)cb * p2_region(H) * cs;
+    if (thr > maxthr_p2 || lds > kLdsBudget || (tn.col_threads > 0 && tn.col_threads != thr))
+      return fail(SEGSALSA_ERR_UNSUPPORTED,
+                  "%lld columns of %d per workgroup (%lld threads, %zu bytes of LDS) do not fit", cb, H, thr, lds);
+    p.cols_per_block = (int)cb;
+    p.col_threads = (int)thr;
+    p.col_ept = 0;
+    p.col_lds = lds;
+  } else {
     const int Lc = p.fcol.blu ? p.fcol.M : H;
     auto lds_of = [&](long long cb) {
       return ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
@@ -505,10 +553,10 @@ void log_plan(const Plan& p) {
     if (lg[0] == '1')
       std::fprintf(stderr,
                    "[segsalsa] plan %s K=%d H=%d W=%d M=%d%s: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
-                   "kpw=%d lds=%zu; rows/block=%d threads=%d ept=%d lds=%zu; cols/block=%d threads=%d ept=%d "
+                   "kpw=%d%s lds=%zu; rows/block=%d threads=%d ept=%d lds=%zu; cols/block=%d threads=%d ept=%d "
                    "lds=%zu; region %zu B\n",
                    p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.tuned ? " (tuned)" : "", p.g.ntr, p.g.ntc, p.g.TR,
-                   p.g.TC, p.g.ntiles(), p.g.steps, p.nw, p.kpw, p.prox_lds, p.rows_per_block, p.row_threads,
+                   p.g.TC, p.g.ntiles(), p.g.steps, p.nw, p.kpw, p.pf ? " prefetch" : "", p.prox_lds, p.rows_per_block, p.row_threads,
                    p.row_ept, p.row_lds, p.cols_per_block, p.col_threads, p.col_ept, p.col_lds, p.total);
   }
 }
@@ -658,10 +706,12 @@ struct LaunchSet {
   struct Group {
     int kpw, nw, first, count, blocks;
     size_t lds;
+    bool pf;
   };
   struct FftGroup {
     int ept, threads, first, count, blocks;
     size_t lds;
+    int p2;   // power-of-two length of the fixed-structure kernels, 0: general kernels
   };
   std::vector<Group> groups;
   std::vector<FftGroup> rgroups, cgroups;
@@ -701,15 +751,16 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return px.nw != py.nw ? px.nw < py.nw : px.kpw < py.kpw;
+    return px.nw != py.nw ? px.nw < py.nw : (px.kpw != py.kpw ? px.kpw < py.kpw : px.pf < py.pf);
   });
   std::vector<ProxArgs<T>> pa(order.size()), pb;
   for (size_t q = 0; q < order.size(); ++q) {
     const ImgRun& r = b.im[order[q]];
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
-    if (ls.groups.empty() || ls.groups.back().nw != p.nw || ls.groups.back().kpw != p.kpw)
-      ls.groups.push_back({p.kpw, p.nw, (int)q, 0, 0, 0});
+    if (ls.groups.empty() || ls.groups.back().nw != p.nw || ls.groups.back().kpw != p.kpw ||
+        ls.groups.back().pf != p.pf)
+      ls.groups.push_back({p.kpw, p.nw, (int)q, 0, 0, 0, p.pf});
     LaunchSet::Group& g = ls.groups.back();
     ProxArgs<T>& a = pa[q];
     std::memset(&a, 0, sizeof(a));
@@ -744,12 +795,12 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
   std::stable_sort(rord.begin(), rord.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return px.row_threads != py.row_threads ? px.row_threads < py.row_threads : px.row_ept < py.row_ept;
+    return std::tie(px.row_p2, px.row_threads, px.row_ept) < std::tie(py.row_p2, py.row_threads, py.row_ept);
   });
   std::stable_sort(cord.begin(), cord.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return px.col_threads != py.col_threads ? px.col_threads < py.col_threads : px.col_ept < py.col_ept;
+    return std::tie(px.col_p2, px.col_threads, px.col_ept) < std::tie(py.col_p2, py.col_threads, py.col_ept);
   });
   std::vector<RowFwdArgs<T>> rf(active.size());
   std::vector<ColArgs<T>> ca(active.size());
@@ -763,8 +814,9 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const ImgRun& r = b.im[rord[q]];
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
-    if (ls.rgroups.empty() || ls.rgroups.back().threads != p.row_threads || ls.rgroups.back().ept != p.row_ept)
-      ls.rgroups.push_back({p.row_ept, p.row_threads, (int)q, 0, 0, 0});
+    if (ls.rgroups.empty() || ls.rgroups.back().threads != p.row_threads || ls.rgroups.back().ept != p.row_ept ||
+        ls.rgroups.back().p2 != p.row_p2)
+      ls.rgroups.push_back({p.row_ept, p.row_threads, (int)q, 0, 0, 0, p.row_p2});
     LaunchSet::FftGroup& g = ls.rgroups.back();
     RowFwdArgs<T>& f = rf[q];
     std::memset(&f, 0, sizeof(f));
@@ -796,8 +848,9 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const ImgRun& r = b.im[cord[q]];
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
-    if (ls.cgroups.empty() || ls.cgroups.back().threads != p.col_threads || ls.cgroups.back().ept != p.col_ept)
-      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0});
+    if (ls.cgroups.empty() || ls.cgroups.back().threads != p.col_threads || ls.cgroups.back().ept != p.col_ept ||
+        ls.cgroups.back().p2 != p.col_p2)
+      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0, p.col_p2});
     LaunchSet::FftGroup& g = ls.cgroups.back();
     ColArgs<T>& k = ca[q];
     std::memset(&k, 0, sizeof(k));
@@ -850,8 +903,9 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t1(1, st);
     const RowFwdArgs<T>* tab = wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]);
     for (const auto& g : ls.rgroups)
-      if ((e = launch_rows_fwd(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
-          hipSuccess)
+      if ((e = g.p2 ? launch_rows_fwd_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                    : launch_rows_fwd(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
+                                      st)) != hipSuccess)
         return e;
     t1.stop();
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -860,7 +914,8 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t2(2, st);
     const ColArgs<T>* tab = wsp<ColArgs<T>>(ws, b.off_tab[3]);
     for (const auto& g : ls.cgroups)
-      if ((e = launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
+      if ((e = g.p2 ? launch_cols_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                    : launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
           hipSuccess)
         return e;
     t2.stop();
@@ -870,8 +925,9 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t3(3, st);
     const RowInvArgs<T>* tab = wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]);
     for (const auto& g : ls.rgroups)
-      if ((e = launch_rows_inv(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
-          hipSuccess)
+      if ((e = g.p2 ? launch_rows_inv_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                    : launch_rows_inv(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
+                                      st)) != hipSuccess)
         return e;
     t3.stop();
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -891,9 +947,10 @@ hipError_t enqueue_round(const Batch& b, const LaunchSet& ls, void* ws, hipStrea
   {
     PhaseTimer t0(0, st);
     for (const auto& g : ls.groups) {
-      // checked rounds (residuals) run the instantiation that accumulates them
-      e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.lds,
-                      b.c.pkind == kSchattenP || b.c.g4s || residuals, st);
+      // checked rounds (residuals) and the variants run the instantiation that has them,
+      // which is built without the prefetch
+      const bool var = b.c.pkind == kSchattenP || b.c.g4s || residuals;
+      e = launch_prox(ptab + g.first, g.count, g.blocks, g.nw * 64, b.c.M, g.kpw, g.pf && !var, g.lds, var, st);
       if (e != hipSuccess) return e;
     }
     t0.stop();
@@ -1122,7 +1179,8 @@ std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, 
   // plan choices that the tuning table can change
   for (size_t i = 0; i < b.im.size(); ++i) {
     const Plan& p = b.im[i].plan;
-    const int pi[] = {p.g.ntr, p.g.ntc, p.kpw, p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads};
+    const int pi[] = {p.g.ntr,          p.g.ntc,       p.kpw,            p.pf ? 1 : 0, p.row_p2,
+                      p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads, p.col_p2};
     key_add(k, pi, sizeof(pi));
   }
   return k;
@@ -1461,6 +1519,9 @@ void tuning_of(const Plan& p, segsalsa_tuning& t) {
   t.tile_rows = p.g.TR;
   t.tile_cols = p.g.TC;
   t.classes_per_wave = p.kpw;
+  t.prefetch = p.pf ? 1 : 0;
+  t.generic_fft = (p.row_p2 == 0 && p2_length(p.W) && !p.frow.blu) || (p.col_p2 == 0 && p2_length(p.H) && !p.fcol.blu)
+                      ? 1 : 0;
   t.rows_per_block = p.rows_per_block;
   t.row_threads = p.row_threads;
   t.cols_per_block = p.cols_per_block;
@@ -1473,6 +1534,9 @@ segsalsa_status check_tuning_fields(const segsalsa_tuning& t) {
     return fail(SEGSALSA_ERR_INVALID_ARG, "tile %dx%d: give both sides > 0 or both 0", t.tile_rows, t.tile_cols);
   if (t.classes_per_wave != 0 && t.classes_per_wave != 1 && t.classes_per_wave != 2 && t.classes_per_wave != 4)
     return fail(SEGSALSA_ERR_INVALID_ARG, "classes_per_wave = %d (0, 1, 2 or 4)", t.classes_per_wave);
+  if (t.prefetch != 0 && t.prefetch != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "prefetch = %d (0 or 1)", t.prefetch);
+  if (t.generic_fft != 0 && t.generic_fft != 1)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "generic_fft = %d (0 or 1)", t.generic_fft);
   if (t.rows_per_block < 0 || t.cols_per_block < 0)
     return fail(SEGSALSA_ERR_INVALID_ARG, "rows/cols per block must be >= 0");
   if (!thr_ok(t.row_threads) || !thr_ok(t.col_threads))
@@ -1533,9 +1597,11 @@ bool json_string(const std::string& obj, const char* key, std::string& v) {
 // Candidate launch shapes of the autotuner for one image shape.
 std::vector<segsalsa_tuning> prox_candidates(int K, int H, int W, const Common& c) {
   std::vector<segsalsa_tuning> out;
-  for (int kpw : {1, 2, 4}) {
+  for (int kp : {1, 2, 4, 102}) {   // 102: two classes per wavefront, prefetching build
+    const int kpw = kp % 100;
     segsalsa_tuning t{};
     t.classes_per_wave = kpw;
+    t.prefetch = kp > 100 ? 1 : 0;
     Plan p;
     const std::string saved = g_last_error;
     if (plan_with(K, H, W, c, t, p) != SEGSALSA_OK) {   // this many classes per wavefront do not fit
@@ -1596,6 +1662,7 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
     cand.tile_rows = pc.tile_rows;
     cand.tile_cols = pc.tile_cols;
     cand.classes_per_wave = pc.classes_per_wave;
+    cand.prefetch = pc.prefetch;
     if (!measure(cand, t, err)) {
       if (err != SEGSALSA_OK) return err;
       continue;
@@ -1614,46 +1681,78 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
     const int Lr = p.frow.blu ? p.frow.M : W;
     segsalsa_tuning win = cur;
     double win_t = cur_rows;
-    for (int rpb : {1, 2, 3, 4, 6, 8, 12, 16}) {
+    auto consider = [&](const segsalsa_tuning& cand) -> segsalsa_status {
+      if (cand.rows_per_block == cur.rows_per_block && cand.row_threads == cur.row_threads &&
+          cand.generic_fft == cur.generic_fft)
+        return SEGSALSA_OK;
+      if (!measure(cand, t, err)) return err;
+      if (t[2] < win_t) {
+        win = cand;
+        win_t = t[2];
+      }
+      return SEGSALSA_OK;
+    };
+    segsalsa_status s2 = SEGSALSA_OK;
+    const bool pow2 = p2_length(W) && !p.frow.blu;
+    if (pow2) {   // the fixed-structure kernels: rows per workgroup (threads follow)
+      for (int rpb : {1, 2, 4, 8, 16}) {
+        if (rpb > H) break;
+        segsalsa_tuning cand = cur;
+        cand.generic_fft = 0;
+        cand.rows_per_block = rpb;
+        cand.row_threads = 0;
+        cand.cols_per_block = cand.col_threads = 0;
+        if ((s2 = consider(cand)) != SEGSALSA_OK) return s2;
+      }
+    }
+    for (int rpb : {1, 2, 3, 4, 6, 8, 12, 16}) {   // the general kernels
       if (rpb > H) break;
       for (int per : {2, 4, 8, 16}) {
         segsalsa_tuning cand = cur;
+        cand.generic_fft = pow2 ? 1 : cur.generic_fft;
+        if (pow2) cand.cols_per_block = cand.col_threads = 0;
         cand.rows_per_block = rpb;
         cand.row_threads = fft_threads_for((long long)rpb * Lr, per);
-        if (cand.rows_per_block == cur.rows_per_block && cand.row_threads == cur.row_threads) continue;
-        if (!measure(cand, t, err)) {
-          if (err != SEGSALSA_OK) return err;
-          continue;
-        }
-        if (t[2] < win_t) {
-          win = cand;
-          win_t = t[2];
-        }
+        if ((s2 = consider(cand)) != SEGSALSA_OK) return s2;
       }
     }
     cur = win;
+    cur_cols = 1e30;   // re-measured below with the chosen row kernels
   }
   // 3. column blocking, by the column pass
   {
     Plan p;
     if (plan_with(K, H, W, c, cur, p) != SEGSALSA_OK) return fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
     const int Lc = p.fcol.blu ? p.fcol.M : H;
+    if (!measure(cur, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
     segsalsa_tuning win = cur;
-    double win_t = cur_cols;
-    for (int cb : {1, 2, 4, 8, 16, 32}) {
-      if (cb > W) break;
-      for (int per : {2, 4, 8, 16}) {
+    double win_t = t[3];
+    auto consider = [&](const segsalsa_tuning& cand) -> segsalsa_status {
+      if (cand.cols_per_block == cur.cols_per_block && cand.col_threads == cur.col_threads) return SEGSALSA_OK;
+      if (!measure(cand, t, err)) return err;
+      if (t[3] < win_t) {
+        win = cand;
+        win_t = t[3];
+      }
+      return SEGSALSA_OK;
+    };
+    segsalsa_status s3 = SEGSALSA_OK;
+    if (p.col_p2) {   // the fixed-structure kernels: columns per workgroup (threads follow)
+      for (int cb : {1, 2, 4, 8, 16}) {
+        if (cb > W) break;
         segsalsa_tuning cand = cur;
         cand.cols_per_block = cb;
-        cand.col_threads = fft_threads_for((long long)cb * Lc, per);
-        if (cand.cols_per_block == cur.cols_per_block && cand.col_threads == cur.col_threads) continue;
-        if (!measure(cand, t, err)) {
-          if (err != SEGSALSA_OK) return err;
-          continue;
-        }
-        if (t[3] < win_t) {
-          win = cand;
-          win_t = t[3];
+        cand.col_threads = 0;
+        if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
+      }
+    } else {
+      for (int cb : {1, 2, 4, 8, 16, 32}) {
+        if (cb > W) break;
+        for (int per : {2, 4, 8, 16}) {
+          segsalsa_tuning cand = cur;
+          cand.cols_per_block = cb;
+          cand.col_threads = fft_threads_for((long long)cb * Lc, per);
+          if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
         }
       }
     }
@@ -2033,11 +2132,12 @@ segsalsa_status segsalsa_tuning_save(const char* path) {
       char buf[512];
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"K\": %d, \"H\": %d, \"W\": %d, \"M\": %d, \"precision\": \"%s\", \"tile_rows\": %d, "
-                    "\"tile_cols\": %d, \"classes_per_wave\": %d, \"rows_per_block\": %d, \"row_threads\": %d, "
-                    "\"cols_per_block\": %d, \"col_threads\": %d, \"us_per_round\": %.3f}",
+                    "\"tile_cols\": %d, \"classes_per_wave\": %d, \"prefetch\": %d, \"generic_fft\": %d, "
+                    "\"rows_per_block\": %d, \"row_threads\": %d, \"cols_per_block\": %d, \"col_threads\": %d, "
+                    "\"us_per_round\": %.3f}",
                     first ? "" : ",", k.K, k.H, k.W, k.M, k.fp64 ? "fp64" : "fp32", t.tile_rows, t.tile_cols,
-                    t.classes_per_wave, t.rows_per_block, t.row_threads, t.cols_per_block, t.col_threads,
-                    t.us_per_round);
+                    t.classes_per_wave, t.prefetch, t.generic_fft, t.rows_per_block, t.row_threads, t.cols_per_block,
+                    t.col_threads, t.us_per_round);
       txt += buf;
       first = false;
     }
@@ -2073,7 +2173,7 @@ segsalsa_status segsalsa_tuning_load(const char* path, int32_t* loaded, int32_t*
     if (end == std::string::npos) break;
     const std::string obj = txt.substr(pos, end - pos + 1);
     pos = end + 1;
-    double K, H, W, M, tr, tc, kpw, rpb, rt, cpb, ct, us = 0.0;
+    double K, H, W, M, tr, tc, kpw, rpb, rt, cpb, ct, us = 0.0, pf = 0.0, gf = 0.0;
     std::string prec;
     if (!(json_number(obj, "K", K) && json_number(obj, "H", H) && json_number(obj, "W", W) &&
           json_number(obj, "M", M) && json_string(obj, "precision", prec) && json_number(obj, "tile_rows", tr) &&
@@ -2085,8 +2185,11 @@ segsalsa_status segsalsa_tuning_load(const char* path, int32_t* loaded, int32_t*
       continue;
     }
     (void)json_number(obj, "us_per_round", us);
+    (void)json_number(obj, "prefetch", pf);
+    (void)json_number(obj, "generic_fft", gf);
     segsalsa_tuning t{};
-    t.tile_rows = (int)tr; t.tile_cols = (int)tc; t.classes_per_wave = (int)kpw;
+    t.tile_rows = (int)tr; t.tile_cols = (int)tc; t.classes_per_wave = (int)kpw; t.prefetch = (int)pf;
+    t.generic_fft = (int)gf;
     t.rows_per_block = (int)rpb; t.row_threads = (int)rt; t.cols_per_block = (int)cpb; t.col_threads = (int)ct;
     t.us_per_round = us;
     if (segsalsa_tuning_set((int)K, (int)H, (int)W, (int)M, prec == "fp64" ? SEGSALSA_FP64 : SEGSALSA_FP32, &t) ==

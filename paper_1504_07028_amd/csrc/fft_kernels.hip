@@ -21,127 +21,9 @@
 // are staged in LDS next to the data.
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
+#include "fft_math.h"
 
 namespace segsalsa {
-
-// Every LDS buffer and table below is passed with its address space spelled
-// out (lptr: LDS, gptr: global): generic pointers would become FLAT
-// instructions, which are slower and make every LDS wait also wait for the
-// outstanding global loads.
-template <typename T>
-using lptr = __attribute__((address_space(3))) T*;
-
-// Complex element loads and stores through those pointers, member by member
-// (the implicit copy operations of C2 only bind to generic addresses).
-template <typename P>
-__device__ __forceinline__ auto ldc(P p) {
-  using T = decltype(+p->x);
-  return C2<T>{p->x, p->y};
-}
-template <typename P, typename V>
-__device__ __forceinline__ void stc(P p, const V& v) {
-  p->x = v.x;
-  p->y = v.y;
-}
-
-template <typename T>
-__device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename T>
-__device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename T>
-__device__ inline C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
-// multiply by +i (sg = +1) or -i (sg = -1)
-template <typename T>
-__device__ inline C2<T> cmuli(C2<T> a, T sg) { return {-sg * a.y, sg * a.x}; }
-// a * w (forward) or a * conj(w) (inverse)
-template <typename T>
-__device__ inline C2<T> twmul(C2<T> a, C2<T> w, bool inv) {
-  const T wy = inv ? -w.y : w.y;
-  return {a.x * w.x - a.y * wy, a.x * wy + a.y * w.x};
-}
-
-// DFT of R values, y_q = sum_r v_r exp(sg 2 pi i r q / R), sg = -1 forward, +1 inverse.
-template <typename T, int R>
-struct Bfly;
-
-template <typename T>
-struct Bfly<T, 2> {
-  __device__ static void run(C2<T>* v, T) {
-    const C2<T> a = v[0], b = v[1];
-    v[0] = cadd(a, b);
-    v[1] = csub(a, b);
-  }
-};
-
-template <typename T>
-struct Bfly<T, 3> {
-  __device__ static void run(C2<T>* v, T sg) {
-    const T h = T(0.86602540378443864676);  // sin(2 pi / 3)
-    const C2<T> t = cadd(v[1], v[2]);
-    const C2<T> d = csub(v[1], v[2]);
-    const C2<T> m = {v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
-    const C2<T> e = cmuli(cscale(d, h), sg);
-    v[0] = cadd(v[0], t);
-    v[1] = cadd(m, e);
-    v[2] = csub(m, e);
-  }
-};
-
-template <typename T>
-struct Bfly<T, 4> {
-  __device__ static void run(C2<T>* v, T sg) {
-    const C2<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-    const C2<T> t2 = cadd(v[1], v[3]), t3 = cmuli(csub(v[1], v[3]), sg);
-    v[0] = cadd(t0, t2);
-    v[2] = csub(t0, t2);
-    v[1] = cadd(t1, t3);
-    v[3] = csub(t1, t3);
-  }
-};
-
-template <typename T>
-struct Bfly<T, 5> {
-  __device__ static void run(C2<T>* v, T sg) {
-    const T c1 = T(0.30901699437494742410);   // cos(2 pi / 5)
-    const T c2 = T(-0.80901699437494742410);  // cos(4 pi / 5)
-    const T s1 = T(0.95105651629515357212);   // sin(2 pi / 5)
-    const T s2 = T(0.58778525229247312917);   // sin(4 pi / 5)
-    const C2<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-    const C2<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-    const C2<T> b1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
-    const C2<T> b2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
-    const C2<T> e1 = cmuli(C2<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, sg);
-    const C2<T> e2 = cmuli(C2<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, sg);
-    v[0] = cadd(v[0], cadd(t1, t2));
-    v[1] = cadd(b1, e1);
-    v[4] = csub(b1, e1);
-    v[2] = cadd(b2, e2);
-    v[3] = csub(b2, e2);
-  }
-};
-
-template <typename T>
-struct Bfly<T, 8> {
-  __device__ static void run(C2<T>* v, T sg) {
-    const T r = T(0.70710678118654752440);  // 1/sqrt(2)
-    C2<T> e[4] = {v[0], v[2], v[4], v[6]};
-    C2<T> o[4] = {v[1], v[3], v[5], v[7]};
-    Bfly<T, 4>::run(e, sg);
-    Bfly<T, 4>::run(o, sg);
-    // o_q *= exp(sg 2 pi i q / 8)
-    const C2<T> o1 = {r * (o[1].x - sg * o[1].y), r * (o[1].y + sg * o[1].x)};
-    const C2<T> o2 = cmuli(o[2], sg);
-    const C2<T> o3 = {r * (-o[3].x - sg * o[3].y), r * (-o[3].y + sg * o[3].x)};
-    v[0] = cadd(e[0], o[0]);
-    v[4] = csub(e[0], o[0]);
-    v[1] = cadd(e[1], o1);
-    v[5] = csub(e[1], o1);
-    v[2] = cadd(e[2], o2);
-    v[6] = csub(e[2], o2);
-    v[3] = cadd(e[3], o3);
-    v[7] = csub(e[3], o3);
-  }
-};
 
 // DFT of an odd prime number P of values in registers, using the pairs
 // (r, P - r): y_q = a_q + sg i b_q and y_(P-q) = a_q - sg i b_q with
@@ -200,6 +82,7 @@ __device__ __forceinline__ void stage_reg(lptr<C2<T>> buf, int N, int nb, int es
   const int NR = N / R;
   const int total = nb * NR;
   const int stw = N / (Ns * R);
+  const FastDiv fnb(nb), fNR(NR), fNs(Ns);
   C2<T> v[IT][R];
   int ob[IT];
 #pragma unroll
@@ -211,13 +94,13 @@ __device__ __forceinline__ void stage_reg(lptr<C2<T>> buf, int N, int nb, int es
       // so one instruction touches one contiguous run of LDS words
       int b, j;
       if (bs == 1) {
-        j = item / nb;
+        j = (int)fnb.div(item);
         b = item - j * nb;
       } else {
-        b = item / NR;
+        b = (int)fNR.div(item);
         j = item - b * NR;
       }
-      const int k = j % Ns;
+      const int k = (int)fNs.mod(j);
       const int base = b * bs;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = ldc(buf + base + (j + r * NR) * es);
@@ -259,18 +142,19 @@ __device__ __forceinline__ void stage_generic(lptr<C2<T>> buf, int N, int R, int
   const int NR = N / R;
   const int total = nb * N;
   const int stw = N / (Ns * R);
+  const FastDiv fnb(nb), fN(N), fNR(NR), fNs(Ns);
   if (Ns > 1) {
     for (int item = threadIdx.x; item < total; item += blockDim.x) {
       int b, rem;
       if (bs == 1) {
-        rem = item / nb;
+        rem = (int)fnb.div(item);
         b = item - rem * nb;
       } else {
-        b = item / N;
+        b = (int)fN.div(item);
         rem = item - b * N;
       }
-      const int r = rem / NR, j = rem - r * NR;
-      const int k = j % Ns;
+      const int r = (int)fNR.div(rem), j = rem - r * NR;
+      const int k = (int)fNs.mod(j);
       if (r > 0 && k > 0) {
         const int idx = b * bs + rem * es;
         stc(buf + idx, twmul(ldc(buf + idx), ldc(tw + r * k * stw), inv));   // r k stw < R Ns stw = N
@@ -288,6 +172,7 @@ __device__ __forceinline__ void stage_generic(lptr<C2<T>> buf, int N, int R, int
   const int half = (R - 1) / 2;
   const int H1 = half + 1;
   const int ptotal = nb * NR * H1;
+  const FastDiv fH1(H1), fNRH1(NR * H1);
   C2<T> oa[EPTP], ob[EPTP];
   int ia[EPTP], ib[EPTP];
 #pragma unroll
@@ -297,14 +182,14 @@ __device__ __forceinline__ void stage_generic(lptr<C2<T>> buf, int N, int R, int
     if (item < ptotal) {
       int b, rem;
       if (bs == 1) {
-        rem = item / nb;
+        rem = (int)fnb.div(item);
         b = item - rem * nb;
       } else {
-        b = item / (NR * H1);
+        b = (int)fNRH1.div(item);
         rem = item - b * (NR * H1);
       }
-      const int j = rem / H1, q = rem - j * H1;
-      const int k = j % Ns;
+      const int j = (int)fH1.div(rem), q = rem - j * H1;
+      const int k = (int)fNs.mod(j);
       const lptr<C2<T>> xj = buf + b * bs + j * es;
       const int sr = NR * es;
       const C2<T> x0 = ldc(xj);
@@ -391,8 +276,9 @@ __device__ __forceinline__ void fft_lds(lptr<C2<T>> buf, const FftPlanDev& p, in
     return;
   }
   const int N = p.N, M = p.M;
+  const int lgM = __builtin_ctz((unsigned)M);   // M is a power of two
   for (int idx = threadIdx.x; idx < nb * M; idx += blockDim.x) {
-    const int b = idx / M, n = idx - b * M;
+    const int b = idx >> lgM, n = idx & (M - 1);
     C2<T> v = {T(0), T(0)};
     if (n < N) {
       C2<T> c = ldc(glob(tab.chirp) + n);
@@ -417,8 +303,9 @@ __device__ __forceinline__ void fft_lds(lptr<C2<T>> buf, const FftPlanDev& p, in
   __syncthreads();
   stockham<T, EPT>(scr, M, p.mnst, p.mrad, nb, 1, M, glob(tab.twM), glob(tab.twM), true);
   const T invM = T(1) / T(M);
+  const FastDiv fN(N);
   for (int idx = threadIdx.x; idx < nb * N; idx += blockDim.x) {
-    const int b = idx / N, k = idx - b * N;
+    const int b = (int)fN.div(idx), k = idx - b * N;
     C2<T> c = ldc(glob(tab.chirp) + k);
     if (inv) c.y = -c.y;
     stc(buf + b * bs + k * es, cscale(cmul(ldc(scr + b * M + k), c), invM));
@@ -490,6 +377,7 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   // right-hand side = sum of the grown-tile partial sums covering (r, c)
   const size_t plane = (size_t)a.g.ER * a.g.EC;
   const bool has1 = k1 < a.K;
+  const FastDiv fW(W);
   // Each thread holds at most EPT of the nb * W elements (blockDim.x * EPT
   // >= nb * W, as the LDS FFT needs): unrolled, so the list and data loads of
   // its elements are in flight together.  The first two entries of each list
@@ -499,7 +387,7 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   for (int it = 0; it < EPT; ++it) {
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < nb * W) {
-      const int rr = idx / W, c = idx - rr * W;
+      const int rr = (int)fW.div(idx), c = idx - rr * W;
       const gptr<const int> rl = frow + (row0 + rr);   // [kFoldStride][H]
       const gptr<const int> cl = fcol + c;             // [kFoldStride][W]
       const int nr = rl[0], nc = cl[0];
@@ -538,6 +426,7 @@ __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __rest
   const int m = bid / ncb;
   const int col0 = (bid - m * ncb) * CB;
   const int nb = min(CB, W - col0);
+  const FastDiv fnb(nb);
   const gptr<C2<T>> sp = glob(a.spec) + (size_t)m * H * W + col0;
   const FftTab<T>& tab = a.tab;
   lptr<C2<T>> tw = buf + CB * H;  // twiddles, or Bluestein scratch
@@ -547,7 +436,7 @@ __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __rest
   for (int it = 0; it < EPT; ++it) {  // blockDim.x * EPT >= H * nb: loads in flight together
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < H * nb) {
-      const int y = idx / nb, j = idx - y * nb;
+      const int y = (int)fnb.div(idx), j = idx - y * nb;
       stc(buf + idx, ldc(sp + (size_t)y * W + j));
     }
   }
@@ -556,14 +445,14 @@ __global__ void __launch_bounds__(MAXT) fft_cols_kernel(const ColArgs<T>* __rest
   fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, tab, tw, false);
   const gptr<const double> sx = glob(a.sx), sy = glob(a.sy);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
-    const int y = idx / nb, j = idx - y * nb;
+    const int y = (int)fnb.div(idx), j = idx - y * nb;
     const T inv = T(a.scale) / (T(3) + T(a.wsum) * T(sx[col0 + j] + sy[y]));
     stc(buf + idx, cscale(ldc(buf + idx), inv));
   }
   __syncthreads();
   fft_lds<T, EPT>(buf, a.plan, nb, nb, 1, tw, tab, tw, true);
   for (int idx = threadIdx.x; idx < H * nb; idx += blockDim.x) {
-    const int y = idx / nb, j = idx - y * nb;
+    const int y = (int)fnb.div(idx), j = idx - y * nb;
     stc(sp + (size_t)y * W + j, ldc(buf + idx));
   }
 }

@@ -30,8 +30,17 @@ namespace segsalsa {
 // VAR compiles in the method's variants (general Schatten p, simplex g4) and
 // the primal-residual accumulation of checked rounds; the plain instantiation
 // (p in {1, 2, inf}, affine g4, no residuals) stays lean.
-template <typename T, int M, int KPW, bool VAR>
-__global__ void __launch_bounds__((prox_max_threads<T, M, KPW>()))
+//
+// PF (prefetch): the loads of step s + 1 (p_hat, d1, d3, d4 and the raw d2
+// pairs of the wavefront's classes) are issued into a second register set at
+// the start of step s's multiplier/scatter phase, so that they stream while
+// that phase computes and stores.  All wavefronts of a workgroup run each
+// step's phases in lockstep (three barriers per step), and without it the
+// loads of a step only start once the previous step's work is done, so the
+// memory and the arithmetic of a step never overlap.  It doubles the per-lane
+// state, hence fewer (and fuller) wavefronts.
+template <typename T, int M, int KPW, bool VAR, bool PF>
+__global__ void __launch_bounds__((prox_max_threads<T, M, KPW, PF>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
   constexpr int L = D * D;
@@ -101,6 +110,33 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   const int nsteps = (P + 63) >> 6;
   const bool want_res = VAR && a.res_tile != nullptr;  // checked rounds use the VAR instantiation
   double rp_acc = 0.0;
+  // prefetched inputs of the next step (PF)
+  constexpr int KP = PF ? KPW : 1, LP = PF ? L : 1;
+  T Pp[KP], P1[KP], P3[KP], P4[KP], Pd[KP][LP][2];
+  // class kk's inputs of step sn (one class at a time, so that in the update
+  // phase the next step's block of a class only becomes live as the current
+  // step's block of the class before it dies)
+  auto prefetch = [&](int sn, int kk) {
+    const bool vn = (sn << 6) + lane < P;
+    const int k = wid + kk * nw;
+    if (k < K && vn) {
+      const size_t kb = ((size_t)tile * g.steps + sn) * K + k;
+      Pp[kk] = gphat[kb * 64 + lane];
+      P1[kk] = gdm[(kb * 3 + 0) * 64 + lane];
+      P3[kk] = gdm[(kb * 3 + 1) * 64 + lane];
+      P4[kk] = gdm[(kb * 3 + 2) * 64 + lane];
+      const gptr<T> d2p = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
+#pragma unroll
+      for (int j = 0; j < LP; ++j) {
+        Pd[kk][j][0] = d2p[j * 128];
+        Pd[kk][j][1] = d2p[j * 128 + 1];
+      }
+    }
+  };
+  if constexpr (PF) {
+#pragma unroll
+    for (int kk = 0; kk < KP; ++kk) prefetch(0, kk);
+  }
   for (int s = 0; s < nsteps; ++s) {
     const int f = (s << 6) + lane;
     const bool valid = f < P;
@@ -117,10 +153,18 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       pk[kk] = v1[kk] = v3[kk] = v4[kk] = T(0);
       if (k < K && valid) {
         const size_t kb = stepbase + k;
-        pk[kk] = gphat[kb * 64 + lane];
-        const T d1 = gdm[(kb * 3 + 0) * 64 + lane];
-        const T d3 = gdm[(kb * 3 + 1) * 64 + lane];
-        const T d4 = gdm[(kb * 3 + 2) * 64 + lane];
+        T d1, d3, d4;
+        if constexpr (PF) {
+          pk[kk] = Pp[kk];
+          d1 = P1[kk];
+          d3 = P3[kk];
+          d4 = P4[kk];
+        } else {
+          pk[kk] = gphat[kb * 64 + lane];
+          d1 = gdm[(kb * 3 + 0) * 64 + lane];
+          d3 = gdm[(kb * 3 + 1) * 64 + lane];
+          d4 = gdm[(kb * 3 + 2) * 64 + lane];
+        }
         const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
         const T zc = zk[0];
         v1[kk] = zc - d1;
@@ -136,7 +180,14 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
           const int dy = j / D - M, dx = j % D - M;
           const T* zr = zk + dy * EC + dx;
           const T z00 = zr[0], z01 = zr[1], z10 = zr[EC];
-          const C2<T> dd = {d2p[j * 128], d2p[j * 128 + 1]};
+          C2<T> dd;
+          if constexpr (PF) {
+            dd.x = Pd[kk][j < LP ? j : 0][0];
+            dd.y = Pd[kk][j < LP ? j : 0][1];
+          } else {
+            dd.x = d2p[j * 128];
+            dd.y = d2p[j * 128 + 1];
+          }
           const T yh = a.c[j] * (z01 - z00) - dd.x;
           const T yv = a.c[j] * (z10 - z00) - dd.y;
           Y[kk][j][0] = yh;
@@ -209,6 +260,8 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
       coef[4 * 64 + lane] = n22 - 1.0;
     }
     __syncthreads();
+    // (with PF, the next step's loads are issued class by class below: a step
+    // other than the last has all its lanes valid, so they are issued by every lane)
     if (valid) {
     const double gain = coef[0 * 64 + lane];
     const double g4c = coef[1 * 64 + lane];
@@ -219,9 +272,12 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
 #pragma unroll
     for (int kk = 0; kk < KPW; ++kk) {
       const int k = wid + kk * nw;
+      if constexpr (PF) {
+        if (s + 1 < nsteps) prefetch(s + 1, kk);   // streams while this class's updates compute and store
+      }
       if (k < K) {
         const size_t kb = stepbase + k;
-        const T d1n = T((double)gphat[kb * 64 + lane] * gain);
+        const T d1n = T((double)pk[kk] * gain);
         const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
         const T d4n = g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
         const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
@@ -326,10 +382,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   }
 }
 
-template <typename T, int M, int KPW, bool VAR>
+template <typename T, int M, int KPW, bool VAR, bool PF>
 static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks, int threads, size_t lds,
                                 hipStream_t st) {
-  auto fn = prox_rhs_kernel<T, M, KPW, VAR>;
+  auto fn = prox_rhs_kernel<T, M, KPW, VAR, PF>;
   static bool lds_set = false;  // idempotent, so a racing second call is harmless
   if (!lds_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -342,39 +398,45 @@ static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks,
 }
 
 template <typename T, int M, bool VAR>
-static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, size_t lds,
+static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, bool pf, size_t lds,
                                 hipStream_t st) {
+  if (pf) {   // built for the plain FP32 kernel with two classes per wavefront and M <= 2 only
+    if constexpr (prox_has_prefetch<T, M, 2, VAR>()) {
+      if (kpw == 2) return launch_prox_t<T, M, 2, VAR, true>(d, n, blocks, threads, lds, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (kpw) {
-    case 1: return launch_prox_t<T, M, 1, VAR>(d, n, blocks, threads, lds, st);
-    case 2: return launch_prox_t<T, M, 2, VAR>(d, n, blocks, threads, lds, st);
-    case 4: return launch_prox_t<T, M, 4, VAR>(d, n, blocks, threads, lds, st);
+    case 1: return launch_prox_t<T, M, 1, VAR, false>(d, n, blocks, threads, lds, st);
+    case 2: return launch_prox_t<T, M, 2, VAR, false>(d, n, blocks, threads, lds, st);
+    case 4: return launch_prox_t<T, M, 4, VAR, false>(d, n, blocks, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, bool VAR>
-static hipError_t launch_prox_v(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
-                                hipStream_t st) {
+static hipError_t launch_prox_v(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, bool pf,
+                                size_t lds, hipStream_t st) {
   switch (M) {
-    case 0: return launch_prox_m<T, 0, VAR>(d, n, blocks, threads, kpw, lds, st);
-    case 1: return launch_prox_m<T, 1, VAR>(d, n, blocks, threads, kpw, lds, st);
-    case 2: return launch_prox_m<T, 2, VAR>(d, n, blocks, threads, kpw, lds, st);
-    case 3: return launch_prox_m<T, 3, VAR>(d, n, blocks, threads, kpw, lds, st);
-    case 4: return launch_prox_m<T, 4, VAR>(d, n, blocks, threads, kpw, lds, st);
-    case 5: return launch_prox_m<T, 5, VAR>(d, n, blocks, threads, kpw, lds, st);
+    case 0: return launch_prox_m<T, 0, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 1: return launch_prox_m<T, 1, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 2: return launch_prox_m<T, 2, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 3: return launch_prox_m<T, 3, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 4: return launch_prox_m<T, 4, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 5: return launch_prox_m<T, 5, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
                        bool variants, hipStream_t st) {
-  return variants ? launch_prox_v<float, true>(d, n, blocks, threads, M, kpw, lds, st)
-                  : launch_prox_v<float, false>(d, n, blocks, threads, M, kpw, lds, st);
+  return variants ? launch_prox_v<float, true>(d, n, blocks, threads, M, kpw, pf, lds, st)
+                  : launch_prox_v<float, false>(d, n, blocks, threads, M, kpw, pf, lds, st);
 }
-hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
                        bool variants, hipStream_t st) {
-  return variants ? launch_prox_v<double, true>(d, n, blocks, threads, M, kpw, lds, st)
-                  : launch_prox_v<double, false>(d, n, blocks, threads, M, kpw, lds, st);
+  return variants ? launch_prox_v<double, true>(d, n, blocks, threads, M, kpw, pf, lds, st)
+                  : launch_prox_v<double, false>(d, n, blocks, threads, M, kpw, pf, lds, st);
 }
 
 }  // namespace segsalsa

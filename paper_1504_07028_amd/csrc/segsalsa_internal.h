@@ -145,6 +145,19 @@ __device__ inline int xcd_block() {
   return base + x * q + (x < r ? x : r) + j;
 }
 
+// Division of small non-negative integers by a divisor known only at run
+// time (a transform length, a block width), as one multiply-high instead of
+// the long instruction sequence of an integer division: with
+// m = ceil(2^32 / d), umulhi(n, m) = floor(n / d) whenever n d < 2^32.
+// Every index divided this way is below 2^15 and every divisor below 2^13;
+// d = 1 (multiplier 2^32) is taken apart.
+struct FastDiv {
+  uint32_t d, m;
+  __device__ explicit FastDiv(uint32_t dd) : d(dd), m(dd > 1 ? 0xFFFFFFFFu / dd + 1u : 0u) {}
+  __device__ uint32_t div(uint32_t n) const { return d == 1 ? n : __umulhi(n, m); }
+  __device__ uint32_t mod(uint32_t n) const { return n - div(n) * d; }
+};
+
 // Per-pixel arithmetic parameters of one round.
 enum PKind : int { kSchatten1 = 1, kSchatten2 = 2, kSchattenInf = 3, kSchattenP = 4 };
 

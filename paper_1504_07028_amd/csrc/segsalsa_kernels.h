@@ -8,20 +8,29 @@ namespace segsalsa {
 // Largest workgroup the prox kernel instantiation <T, M, KPW> is compiled for:
 // each lane keeps KPW classes x 2L entries of the J-split block in registers,
 // so the wavefronts per SIMD (and hence per workgroup) shrink as L grows.
-template <typename T, int M, int KPW>
+template <typename T, int M, int KPW, bool PF = false>
 __host__ __device__ constexpr int prox_max_threads() {
   constexpr int L = (2 * M + 1) * (2 * M + 1);
-  constexpr int vg = KPW * 2 * L * (int)(sizeof(T) / 4) + 48;
+  constexpr int vg = (PF ? 2 : 1) * KPW * 2 * L * (int)(sizeof(T) / 4) + (PF ? 56 : 48);
   constexpr int wps = 512 / vg;
   constexpr int w = wps >= 4 ? 4 : (wps < 1 ? 1 : wps);
   return w * 4 * 64;
 }
 
-inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
+// The prefetching build of the prox kernel exists for the plain FP32 kernel
+// with two classes per wavefront and patches up to 5x5.
+template <typename T, int M, int KPW, bool VAR>
+__host__ __device__ constexpr bool prox_has_prefetch() {
+  return sizeof(T) == 4 && KPW == 2 && M <= 2 && !VAR;
+}
+inline bool prox_has_prefetch_rt(bool fp64, int M, int kpw) { return !fp64 && kpw == 2 && M <= 2; }
+
+inline int prox_max_threads_rt(bool fp64, int M, int kpw, bool pf = false) {
 #define SEG_CASE(MM)                                                                                         \
   case MM:                                                                                                   \
     if (fp64) return kpw == 1 ? prox_max_threads<double, MM, 1>() : kpw == 2 ? prox_max_threads<double, MM, 2>() \
                                                                            : prox_max_threads<double, MM, 4>(); \
+    if (pf) return prox_max_threads<float, MM, 2, true>();                                                   \
     return kpw == 1 ? prox_max_threads<float, MM, 1>() : kpw == 2 ? prox_max_threads<float, MM, 2>()           \
                                                                  : prox_max_threads<float, MM, 4>();
   switch (M) {
@@ -39,9 +48,10 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw) {
 // Per-round launches over a table of per-image descriptors in device memory.
 // variants: the instantiation with the general Schatten p, the simplex g4 and the
 // primal-residual accumulation compiled in (required for descriptors with res_tile set)
-hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+// pf: the prefetching build (prox_has_prefetch; only without variants)
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
                        bool variants, hipStream_t st);
-hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, size_t lds,
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
                        bool variants, hipStream_t st);
 
 // FFT passes; narrow (FP64 only): the instantiation built for at most 512
@@ -58,6 +68,23 @@ hipError_t launch_rows_inv(const RowInvArgs<float>* d, int n, int blocks, int ep
                            hipStream_t st);
 hipError_t launch_rows_inv(const RowInvArgs<double>* d, int n, int blocks, int ept, int threads, bool narrow, size_t lds,
                            hipStream_t st);
+
+// FFT passes for power-of-two lengths N in 64 .. 4096 (fft_pow2_kernels.hip):
+// N / 16 threads per transform, so threads = (rows or columns per block) * N / 16.
+hipError_t launch_rows_fwd_p2(const RowFwdArgs<float>* d, int n, int blocks, int N, int threads, size_t lds,
+                              hipStream_t st);
+hipError_t launch_rows_fwd_p2(const RowFwdArgs<double>* d, int n, int blocks, int N, int threads, size_t lds,
+                              hipStream_t st);
+hipError_t launch_cols_p2(const ColArgs<float>* d, int n, int blocks, int N, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols_p2(const ColArgs<double>* d, int n, int blocks, int N, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv_p2(const RowInvArgs<float>* d, int n, int blocks, int N, int threads, size_t lds,
+                              hipStream_t st);
+hipError_t launch_rows_inv_p2(const RowInvArgs<double>* d, int n, int blocks, int N, int threads, size_t lds,
+                              hipStream_t st);
+constexpr int kP2Min = 64, kP2Max = 4096;
+inline bool p2_length(int n) { return n >= kP2Min && n <= kP2Max && (n & (n - 1)) == 0; }
+// LDS elements per transform of the power-of-two kernels (one pad element every 16, plus one)
+inline size_t p2_region(int n) { return (size_t)n + n / 16 + 1; }
 
 // Set-up, initialisation and data-movement kernels (misc_kernels.hip).
 template <typename T>

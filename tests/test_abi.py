@@ -237,7 +237,7 @@ def test_tuning_set_get_and_workspace(clean_table):
     assert not tuned and plan["tile_rows"] > 0 and plan["row_threads"] % 64 == 0
     st, before = status_of_size(S, base_problem(S, K=K, H=H, W=W))
     assert st == OK
-    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, rows_per_block=3, row_threads=128, cols_per_block=4,
+    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, prefetch=1, generic_fft=0, rows_per_block=3, row_threads=128, cols_per_block=4,
                 col_threads=192, us_per_round=12.5)
     S.segsalsa_tuning_set(K, H, W, M, 0, want)
     got, tuned = S.segsalsa_tuning_get(K, H, W, M, 0)
@@ -257,6 +257,8 @@ def test_tuning_set_get_and_workspace(clean_table):
     (dict(col_threads=2048), INVALID),
     (dict(tile_rows=40, tile_cols=60, classes_per_wave=1), UNSUPPORTED),   # grown tile beyond LDS
     (dict(rows_per_block=40, row_threads=64), UNSUPPORTED),               # 40 x 60 elements > 16 per thread
+    (dict(prefetch=2), INVALID),
+    (dict(prefetch=1, classes_per_wave=1), UNSUPPORTED),                  # prefetching build: 2 classes per wave
 ])
 def test_tuning_rejects_entries_that_do_not_fit(clean_table, bad, code):
     S = clean_table
@@ -325,3 +327,14 @@ def test_autotune_argument_errors(S):
                                          None) == INVALID          # z_scratch aliases input
     assert S.lib().segsalsa_str_autotune(ctypes.byref(s), 0, dummy, ctypes.c_void_p(512), dummy, n.value, 0,
                                          ctypes.byref(t), None) == INVALID   # rounds out of range
+
+
+def test_prefetch_entries_only_where_built(clean_table):
+    S = clean_table
+    S.segsalsa_tuning_set(16, 40, 60, 2, 0, dict(classes_per_wave=2, prefetch=1))
+    got, tuned = S.segsalsa_tuning_get(16, 40, 60, 2, 0)
+    assert tuned and got["prefetch"] == 1 and got["classes_per_wave"] == 2
+    for prec, M in ((1, 2), (0, 3)):      # FP64, or a 7x7 patch: not built
+        with pytest.raises(S.SegsalsaError) as e:
+            S.segsalsa_tuning_set(16, 40, 60, M, prec, dict(classes_per_wave=2, prefetch=1))
+        assert e.value.status == UNSUPPORTED

@@ -32,6 +32,14 @@ SMALL_CASES = [
     (97, 509, 3, 1, 1.0, 4),     # a direct 97-point stage; Bluestein (M = 1024) for 509
     (122, 86, 5, 2, math.inf, 4),  # 2 x 61 and 2 x 43
     (211, 101, 2, 1, 1.0, 3),    # primes just above the direct-stage limit: Bluestein both ways
+    # power-of-two sides (the fixed-structure kernels, 64 .. 4096), alone or next to a general side
+    (64, 128, 5, 1, 1.0, 5),
+    (128, 64, 16, 2, math.inf, 4),
+    (256, 512, 3, 1, 2.0, 3),
+    (64, 96, 4, 1, 1.0, 4),
+    (100, 256, 6, 0, 1.0, 4),
+    (1024, 8, 2, 1, 1.0, 3),     # 1024-point columns (three stages: 16, 16, 4)
+    (8, 4096, 3, 1, 1.0, 3),     # 4096-point rows (16, 16, 16)
 ]
 
 

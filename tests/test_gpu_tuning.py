@@ -76,3 +76,30 @@ def test_autotune_then_solve_matches_oracle(table, dtype):
     err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
     say(f"  max |z_gpu - z_oracle| = {err:.3e}")
     check_err(err, dtype)
+
+
+PF_CASES = [(64, 96, 16, 2), (45, 70, 9, 2), (37, 61, 6, 1), (29, 40, 5, 0)]
+
+
+@pytest.mark.parametrize("case", range(len(PF_CASES)))
+def test_prefetching_prox_build_matches_oracle(table, case):
+    """FP32 prox kernel that loads step s + 1 during step s (two classes per wavefront, odd K pads)."""
+    S = table
+    H, W, K, M = PF_CASES[case]
+    S.segsalsa_tuning_set(K, H, W, M, S.SEGSALSA_FP32, dict(classes_per_wave=2, prefetch=1, tile_rows=8,
+                                                             tile_cols=16))
+    plan, tuned = S.segsalsa_tuning_get(K, H, W, M, S.SEGSALSA_FP32)
+    assert tuned and plan["prefetch"] == 1
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=400 + case)
+    iters = 9
+    say(f"case prefetch {H}x{W} K={K} M={M}: {plan}")
+    z, _, _, _ = gpu_solve(S, probs, c, M, 1.0, 0.8, 1.1, iters, torch.float32)
+    zo = oracle_solve(rounded_input(probs, torch.float32), weights_as_seen(c, torch.float32), M, 1.0, 0.8, 1.1, iters)
+    err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
+    say(f"  max |z_gpu - z_oracle| = {err:.3e}")
+    check_err(err, torch.float32)
+    # the same plan without the prefetch gives the same z bit for bit (same arithmetic, same order)
+    S.segsalsa_tuning_set(K, H, W, M, S.SEGSALSA_FP32, dict(classes_per_wave=2, prefetch=0, tile_rows=8,
+                                                             tile_cols=16))
+    z2, _, _, _ = gpu_solve(S, probs, c, M, 1.0, 0.8, 1.1, iters, torch.float32)
+    assert torch.equal(z, z2)
