@@ -123,10 +123,10 @@ def cpu_baseline(wl, probs, weights, budget_s: float, crop: int = 256):
                        f"{dt:.1f} s; host reports {os.cpu_count()} logical CPUs")
 
 
-def bench_adjoint(S, torch, synth, steps, warmup, ck=10):
+def bench_adjoint(S, torch, synth, steps, warmup, ck=0):
     """Differentiable solve on the 256x256, K = 8, 3x3-patch, 50-round workload: one step is the
     checkpointed forward plus the reverse sweep (gradients w.r.t. logits, lambda, patch weights)
-    of the cross-entropy of z against the label map."""
+    of the cross-entropy of z against the label map.  ck = 0: the library's checkpoint interval."""
     wl = synth.WORKLOADS["diff_256x256_k8"]
     d = synth.make_workload(wl)
     units = wl.n * wl.K * wl.iters
@@ -136,6 +136,7 @@ def bench_adjoint(S, torch, synth, steps, warmup, ck=10):
         x = torch.from_numpy(d["logits"]).to(device="cuda", dtype=dtype)
         pr = S.Problem(wl.K, wl.H, wl.W, wl.M, d["weights"], wl.schatten_p, wl.lam, wl.mu, wl.iters,
                        input_is_logits=True)
+        out["checkpoint_interval_" + tag] = S.segsalsa_str_grad_checkpoint_interval(pr, S._prec(dtype), ck)
         ws = torch.empty(S.segsalsa_str_grad_workspace_size(pr, S._prec(dtype), ck), dtype=torch.uint8,
                          device="cuda")
         z = torch.empty_like(x)
@@ -239,8 +240,18 @@ def bench_sweep(S, torch, synth, wl_name="pines_145x145_k16", radii=(0, 1, 2, 3,
     return out
 
 
-def plan_record(S, K, H, W, M, prec):
+def plan_record(S, K, H, W, M, prec, batch=False):
+    """The launch shapes of one image shape; batch=True: those of an image inside a batch of several,
+    which keeps the planner's shapes even where the tuning table has an entry."""
     t, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+    if batch and tuned:
+        entry = t
+        S.segsalsa_tuning_set(K, H, W, M, prec, None)
+        try:
+            t, _ = S.segsalsa_tuning_get(K, H, W, M, prec)
+        finally:
+            S.segsalsa_tuning_set(K, H, W, M, prec, entry)
+        tuned = False
     rec = {k: v for k, v in t.items() if k != "us_per_round"}
     rec["tuned"] = tuned
     return rec
@@ -292,7 +303,8 @@ def bench_batch(S, torch, synth, steps, warmup, fp32_only=False, graph=True):
            "round_roofline": round_roofline(n_units, L, round_us),
            "z_err_fp32_vs_fp64": z_err,
            "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in out["f32"]["phases"].items()},
-           "plans": [dict(K=K, H=H, W=W, **plan_record(S, K, H, W, B["M"], S.SEGSALSA_FP32)) for (H, W, K) in shapes]}
+           "plans": [dict(K=K, H=H, W=W, **plan_record(S, K, H, W, B["M"], S.SEGSALSA_FP32, batch=True))
+                     for (H, W, K) in shapes]}
     if "f64" in out:
         res["fp64"] = {"value": out["f64"]["value"], "ms_per_step": out["f64"]["ms_per_step"]}
         res["speedup_fp32_vs_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
@@ -328,8 +340,8 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (for profiler runs)")
     ap.add_argument("--no-graph", action="store_true", help="launch the kernels directly instead of one graph")
     ap.add_argument("--tune", action="store_true",
-                    help="run the autotuner on every workload shape (the 64 batch images included) in FP32 and "
-                         "FP64 and write the package's tuning cache")
+                    help="run the autotuner on every single-image workload shape in FP32 and FP64 and write the "
+                         "package's tuning cache")
     ap.add_argument("--tune-rounds", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 512 MiB device-to-device copy (reference for HBM counters)")
@@ -363,8 +375,8 @@ def main():
 
     if args.tune:
         from paper_1504_07028_amd import autotune
+        # single-image workloads only: batches of several images keep the planner's shapes
         shapes = [(w.K, w.H, w.W, w.M) for w in synth.WORKLOADS.values()]
-        shapes += sorted({(K, H, W, synth.BATCH["M"]) for (H, W, K) in synth.batch_shapes()})
         t0 = time.perf_counter()
         res = autotune.tune_shapes(shapes, ["fp32", "fp64"], args.tune_rounds, S.DEFAULT_TUNING_CACHE, fresh=True,
                                    log=log)

@@ -259,7 +259,11 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
  * segsalsa_str_solve_ckpt runs prob->iters rounds like segsalsa_str_solve
  * (same z_out) and keeps, in `workspace`, the state (z, d1..d4) at rounds 0,
  * S, 2S, ... with S = checkpoint_every (clamped to [1, iters]) and the final
- * z.  segsalsa_str_backward then, given dL/dz_out, recomputes each segment of
+ * z.  checkpoint_every = 0 picks S: the smallest interval whose kept states
+ * (ceil(iters / S) checkpoints and S - 1 recomputed ones) take at most 8 GiB,
+ * else ceil(sqrt(iters)); S = 1 keeps every state and recomputes nothing.
+ * The rounds write each state straight into its slot (no copies).
+ * segsalsa_str_backward then, given dL/dz_out, recomputes each segment of
  * S rounds from its checkpoint and runs the reverse rounds, and writes
  *   grad_input    [K][H][W]  dL/d input (probabilities or logits, as given);
  *   grad_lambda   DEVICE, 1 double, dL/d lambda (may be NULL);
@@ -277,6 +281,9 @@ segsalsa_status segsalsa_str_state_import(const segsalsa_problem *prob, segsalsa
  */
 segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem *prob, segsalsa_precision precision,
                                                  int32_t checkpoint_every, size_t *bytes /* HOST, out */);
+/* The interval S that checkpoint_every (0 = automatic) resolves to for this problem. */
+segsalsa_status segsalsa_str_grad_checkpoint_interval(const segsalsa_problem *prob, segsalsa_precision precision,
+                                                      int32_t checkpoint_every, int32_t *interval /* HOST, out */);
 segsalsa_status segsalsa_str_solve_ckpt(const segsalsa_problem *prob, segsalsa_precision precision,
                                         int32_t checkpoint_every, const void *input, void *z_out, void *workspace,
                                         size_t workspace_bytes, hipStream_t stream);
@@ -291,8 +298,11 @@ segsalsa_status segsalsa_str_backward(const segsalsa_problem *prob, segsalsa_pre
  * classes per wavefront and the blocking of the FFT passes from a cost
  * model.  A process-wide tuning table, filled by segsalsa_str_autotune
  * (measured on the device) or by the caller, overrides those choices for the
- * shapes it holds; forward solves and batches of such images then use the
- * tuned shapes (the differentiable solve keeps the planner's).  A tuned entry
+ * shapes it holds in forward solves of one image (segsalsa_str_solve, the
+ * graph and no-allocation variants).  The differentiable solve and batches of
+ * more than one image keep the planner's shapes: the entries are measured
+ * with the image alone on the device, while a batch's images share it and
+ * the planner's shapes group them into fewer launches.  A tuned entry
  * changes the launch shapes and the workspace size, not the arithmetic: the
  * results agree with untuned ones to rounding (the fold and the class sums
  * are added in another order).  Size workspaces after changing the table.

@@ -543,10 +543,13 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   return SEGSALSA_OK;
 }
 
-// Per-image plan: the tuned entry of the shape if there is one and it fits
-// this problem (forward solves only: the differentiable solve sizes its tiles
-// for the reverse sweep too, and the simplex g4 needs more LDS), else the
-// planner's own choices.
+// Per-image plan: the tuned entry of the shape if there is one, the solve is
+// of one image and the entry fits this problem (forward solves only: the
+// differentiable solve sizes its tiles for the reverse sweep too, and the
+// simplex g4 needs more LDS), else the planner's own choices.  The entries
+// are measured with the image alone on the device; the images of a batch
+// share it, and the planner's shapes (sized on each image's own work) group
+// into fewer, fuller launches there.
 void log_plan(const Plan& p) {
   const int K = p.K, H = p.H, W = p.W;
   if (const char* lg = std::getenv("SEGSALSA_LOG")) {
@@ -561,9 +564,9 @@ void log_plan(const Plan& p) {
   }
 }
 
-segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p) {
+segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p, bool use_table = true) {
   segsalsa_tuning tn{};
-  if (!c.grad && tuning_lookup(K, H, W, c.M, c.fp64, tn)) {
+  if (use_table && !c.grad && tuning_lookup(K, H, W, c.M, c.fp64, tn)) {
     const std::string saved = g_last_error;
     if (plan_with(K, H, W, c, tn, p) == SEGSALSA_OK) {
       p.tuned = true;
@@ -683,7 +686,8 @@ segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, cons
   for (int i = 0; i < n; ++i) {
     segsalsa_status s = validate_image(K[i], H[i], W[i], lam[i], mu[i]);
     if (s != SEGSALSA_OK) return fail(s, "image %d: %s", i, segsalsa_last_error());
-    s = force ? plan_with(K[i], H[i], W[i], c, *force, b.im[i].plan) : make_image_plan(K[i], H[i], W[i], c, b.im[i].plan);
+    s = force ? plan_with(K[i], H[i], W[i], c, *force, b.im[i].plan)
+              : make_image_plan(K[i], H[i], W[i], c, b.im[i].plan, n == 1);
     if (s != SEGSALSA_OK) return s;
     b.im[i].base = off;
     b.im[i].lambda = lam[i];
@@ -772,6 +776,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     a.phat = wsp<T>(base, p.off_phat);
     a.dm = wsp<T>(base, p.off_dm);
     a.d2 = wsp<T>(base, p.off_d2);
+    a.dm_in = a.dm;
+    a.d2_in = a.d2;
     a.acc = wsp<T>(base, p.off_acc);
     a.res_tile = nullptr;
     a.mu = r.mu;
@@ -1315,11 +1321,28 @@ struct GradLayout {
   size_t seg(int i) const { return off_seg + (size_t)i * (zbytes + sbytes); }
 };
 
+// checkpoint_every = 0: the smallest interval whose kept states, ceil(N / S)
+// checkpoints and S - 1 recomputed ones, fit in kAutoStateBytes (S = 1 keeps
+// every state and recomputes nothing), else ceil(sqrt(N)).
+constexpr size_t kAutoStateBytes = (size_t)8 << 30;
+
+int auto_interval(int N, size_t state_bytes) {
+  if (N <= 1) return 1;
+  for (int S = 1; S <= N; ++S) {
+    const size_t kept = (size_t)ceil_div(N, S) + (size_t)(S - 1);
+    if (kept * state_bytes <= kAutoStateBytes) return S;
+    if ((long long)S * S >= N) break;   // past the minimum of ceil(N / S) + S - 1
+  }
+  int S = 1;
+  while ((long long)S * S < N) ++S;
+  return S;
+}
+
 segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision prec, int every_ck, GradLayout& gl) {
   Common c{};
   segsalsa_status s = validate_problem(pr, prec, c);
   if (s != SEGSALSA_OK) return s;
-  if (every_ck < 1) return fail(SEGSALSA_ERR_INVALID_ARG, "checkpoint_every = %d < 1", every_ck);
+  if (every_ck < 0) return fail(SEGSALSA_ERR_INVALID_ARG, "checkpoint_every = %d < 0", every_ck);
   if (c.every > 0 || c.tol > 0.0)
     return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve runs a fixed number of rounds (no residual_every/tol)");
   if (c.warm) return fail(SEGSALSA_ERR_UNSUPPORTED, "the differentiable solve starts from the input (no warm_start)");
@@ -1330,11 +1353,12 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
   c.grad = 1;
   if ((s = make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, gl.b)) != SEGSALSA_OK) return s;
   const Plan& p = gl.b.im[0].plan;
+  gl.zbytes = align_up((size_t)p.K * p.H * p.W * p.ts);
+  gl.sbytes = p.off_acc - p.off_dm;
+  if (every_ck == 0) every_ck = auto_interval(c.iters, gl.zbytes + gl.sbytes);
   gl.S = std::max(1, std::min(every_ck, std::max(1, c.iters)));
   gl.nck = c.iters == 0 ? 1 : ceil_div(c.iters, gl.S);
   gl.nseg = gl.S - 1;
-  gl.zbytes = align_up((size_t)p.K * p.H * p.W * p.ts);
-  gl.sbytes = p.off_acc - p.off_dm;
   const size_t nt = (size_t)p.g.ntiles();
   size_t off = gl.b.total;
   gl.off_zw = off; off = align_up(off + gl.zbytes);
@@ -1351,19 +1375,63 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
   return SEGSALSA_OK;
 }
 
-// (z, multipliers) of the working region <-> a slot at `slot` (z first).
-hipError_t save_state(const GradLayout& gl, void* ws, size_t slot, hipStream_t st) {
+// One state (z and the multipliers) of the differentiable solve: the working
+// region of the plan, or a slot (z first, then the multipliers in the plan's
+// layout).
+struct StateRef {
+  char* z;
+  char* dm;
+  char* d2;
+};
+
+StateRef working_state(const GradLayout& gl, void* ws) {
   const Plan& p = gl.b.im[0].plan;
-  hipError_t e = launch_copy_bytes(wsp<char>(ws, slot), wsp<char>(ws, gl.off_zw), gl.zbytes, st);
-  if (e != hipSuccess) return e;
-  return launch_copy_bytes(wsp<char>(ws, slot + gl.zbytes), wsp<char>(ws, p.off_dm), gl.sbytes, st);
+  return {wsp<char>(ws, gl.off_zw), wsp<char>(ws, p.off_dm), wsp<char>(ws, p.off_d2)};
 }
 
-hipError_t load_state(const GradLayout& gl, void* ws, size_t slot, hipStream_t st) {
+StateRef slot_state(const GradLayout& gl, void* ws, size_t slot) {
   const Plan& p = gl.b.im[0].plan;
-  hipError_t e = launch_copy_bytes(wsp<char>(ws, gl.off_zw), wsp<char>(ws, slot), gl.zbytes, st);
+  return {wsp<char>(ws, slot), wsp<char>(ws, slot + gl.zbytes), wsp<char>(ws, slot + gl.zbytes + (p.off_d2 - p.off_dm))};
+}
+
+// The pointers of ProxArgs that name the round's input and output state, in
+// declaration order (z .. d2), stored over the descriptor in one piece.
+template <typename T>
+struct ProxStatePtrs {
+  const T* z;
+  const T* phat;
+  const T* dm_in;
+  const T* d2_in;
+  T* dm;
+  T* d2;
+};
+static_assert(offsetof(ProxArgs<float>, acc) - offsetof(ProxArgs<float>, z) == sizeof(ProxStatePtrs<float>),
+              "ProxArgs state pointers are not contiguous");
+static_assert(offsetof(ProxArgs<double>, acc) - offsetof(ProxArgs<double>, z) == sizeof(ProxStatePtrs<double>),
+              "ProxArgs state pointers are not contiguous");
+static_assert(sizeof(ProxStatePtrs<double>) <= (size_t)kStorePairMax, "state pointers exceed one store");
+
+// One forward round of the single image from state `in` into state `out`
+// (the same region for an update in place): the round's prox descriptor
+// and inverse row descriptor are pointed at the two states, then the round
+// runs as usual.  No state is copied.
+template <typename T>
+hipError_t enqueue_round_states(const GradLayout& gl, const LaunchSet& ls, void* ws, const StateRef& in,
+                                const StateRef& out, hipStream_t st) {
+  const Batch& b = gl.b;
+  const Plan& p = b.im[0].plan;
+  ProxStatePtrs<T> sp;
+  sp.z = reinterpret_cast<const T*>(in.z);
+  sp.phat = wsp<T>(ws, b.im[0].base + p.off_phat);
+  sp.dm_in = reinterpret_cast<const T*>(in.dm);
+  sp.d2_in = reinterpret_cast<const T*>(in.d2);
+  sp.dm = reinterpret_cast<T*>(out.dm);
+  sp.d2 = reinterpret_cast<T*>(out.d2);
+  T* zout = reinterpret_cast<T*>(out.z);
+  hipError_t e = launch_store_pair(wsp<char>(ws, b.off_tab[0] + offsetof(ProxArgs<T>, z)), &sp, sizeof(sp),
+                                   wsp<char>(ws, b.off_tab[4] + offsetof(RowInvArgs<T>, z)), &zout, sizeof(zout), st);
   if (e != hipSuccess) return e;
-  return launch_copy_bytes(wsp<char>(ws, p.off_dm), wsp<char>(ws, slot + gl.zbytes), gl.sbytes, st);
+  return enqueue_round<T>(b, ls, ws, st, false);
 }
 
 template <typename T>
@@ -1374,15 +1442,28 @@ segsalsa_status forward_ckpt_t(const GradLayout& gl, void* ws, const void* input
   LaunchSet ls;
   hipError_t e = enqueue_prepare<T>(b, ws, zs, ins, st, ls, true);
   if (e != hipSuccess) return hip_fail(e, "forward set-up");
-  for (int t = 0; t < b.c.iters; ++t) {
-    if (t % gl.S == 0 && (e = save_state(gl, ws, gl.ck(t / gl.S), st)) != hipSuccess) return hip_fail(e, "checkpoint");
-    if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return hip_fail(e, "forward round");
+  // the initial state is the first checkpoint; every round then reads its
+  // input state where the previous one wrote it and writes the next state
+  // into its checkpoint slot (rounds S, 2S, ...), into zN (the last round's
+  // z), or in place in the working region
+  const StateRef wk = working_state(gl, ws);
+  const StateRef c0 = slot_state(gl, ws, gl.ck(0));
+  if ((e = launch_copy_bytes(c0.z, wk.z, gl.zbytes, st)) != hipSuccess ||
+      (e = launch_copy_bytes(c0.dm, wk.dm, gl.sbytes, st)) != hipSuccess)
+    return hip_fail(e, "checkpoint");
+  const int N = b.c.iters;
+  StateRef in = c0;
+  for (int t = 0; t < N; ++t) {
+    StateRef out = wk;
+    if (t + 1 == N) out.z = wsp<char>(ws, gl.off_zN);
+    else if ((t + 1) % gl.S == 0) out = slot_state(gl, ws, gl.ck((t + 1) / gl.S));
+    if ((e = enqueue_round_states<T>(gl, ls, ws, in, out, st)) != hipSuccess) return hip_fail(e, "forward round");
+    in = out;
   }
-  if (b.c.iters == 0 && (e = save_state(gl, ws, gl.ck(0), st)) != hipSuccess) return hip_fail(e, "checkpoint");
-  if ((e = launch_copy_bytes(wsp<char>(ws, gl.off_zN), zs[0], gl.zbytes, st)) != hipSuccess)
+  if (N == 0 && (e = launch_copy_bytes(wsp<char>(ws, gl.off_zN), wk.z, gl.zbytes, st)) != hipSuccess)
     return hip_fail(e, "final z");
-  if ((e = launch_copy_bytes(z_out, zs[0], (size_t)b.im[0].plan.K * b.im[0].plan.H * b.im[0].plan.W * b.c.ts, st)) !=
-      hipSuccess)
+  const Plan& p = b.im[0].plan;
+  if ((e = launch_copy_bytes(z_out, wsp<char>(ws, gl.off_zN), (size_t)p.K * p.H * p.W * b.c.ts, st)) != hipSuccess)
     return hip_fail(e, "z_out");
   return SEGSALSA_OK;
 }
@@ -1442,12 +1523,12 @@ segsalsa_status backward_t(const GradLayout& gl, void* ws, const void* input, co
   const int N = b.c.iters;
   for (int sg = gl.nck - 1; sg >= 0 && N > 0; --sg) {
     const int t0 = sg * gl.S, t1 = std::min(t0 + gl.S, N);
-    if (t1 - t0 > 1) {  // recompute the segment's states from its checkpoint
-      if ((e = load_state(gl, ws, gl.ck(sg), st)) != hipSuccess) return hip_fail(e, "restore");
-      for (int t = t0 + 1; t < t1; ++t) {
-        if ((e = enqueue_round<T>(b, ls, ws, st, false)) != hipSuccess) return hip_fail(e, "recompute");
-        if ((e = save_state(gl, ws, gl.seg(t - t0 - 1), st)) != hipSuccess) return hip_fail(e, "segment");
-      }
+    // recompute the segment's states from its checkpoint, each round from
+    // one slot into the next
+    for (int t = t0; t + 1 < t1; ++t) {
+      const StateRef in = t == t0 ? slot_state(gl, ws, gl.ck(sg)) : slot_state(gl, ws, gl.seg(t - t0 - 1));
+      if ((e = enqueue_round_states<T>(gl, ls, ws, in, slot_state(gl, ws, gl.seg(t - t0)), st)) != hipSuccess)
+        return hip_fail(e, "recompute");
     }
     for (int t = t1 - 1; t >= t0; --t) {
       if ((e = enqueue_fft<T>(b, ls, ws, st, 5, 6)) != hipSuccess) return hip_fail(e, "adjoint solve");
@@ -2001,6 +2082,17 @@ segsalsa_status segsalsa_str_grad_workspace_size(const segsalsa_problem* prob, s
   segsalsa_status s = make_grad_layout(prob, precision, checkpoint_every, gl);
   if (s != SEGSALSA_OK) return s;
   *bytes = gl.total;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_grad_checkpoint_interval(const segsalsa_problem* prob, segsalsa_precision precision,
+                                                      int32_t checkpoint_every, int32_t* interval) {
+  g_last_error.clear();
+  if (!interval) return fail(SEGSALSA_ERR_INVALID_ARG, "interval is NULL");
+  GradLayout gl;
+  segsalsa_status s = make_grad_layout(prob, precision, checkpoint_every, gl);
+  if (s != SEGSALSA_OK) return s;
+  *interval = gl.S;
   return SEGSALSA_OK;
 }
 

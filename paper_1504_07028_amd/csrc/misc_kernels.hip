@@ -1,4 +1,5 @@
 // Set-up, initialisation, layout conversion and read-out kernels.
+#include <cstring>
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
 
@@ -150,6 +151,31 @@ hipError_t launch_store(void* dst, const void* src, size_t n, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+struct StorePair {
+  unsigned char* dst[2];
+  int n[2];
+  unsigned char b[2][kStorePairMax];
+};
+
+__global__ void store_pair_kernel(StorePair sp) {
+  for (int q = 0; q < 2; ++q)
+    for (int i = threadIdx.x; i < sp.n[q]; i += blockDim.x) sp.dst[q][i] = sp.b[q][i];
+}
+
+hipError_t launch_store_pair(void* dst0, const void* src0, size_t n0, void* dst1, const void* src1, size_t n1,
+                             hipStream_t st) {
+  if (n0 > (size_t)kStorePairMax || n1 > (size_t)kStorePairMax) return hipErrorInvalidValue;
+  StorePair sp;
+  sp.dst[0] = reinterpret_cast<unsigned char*>(dst0);
+  sp.dst[1] = reinterpret_cast<unsigned char*>(dst1);
+  sp.n[0] = (int)n0;
+  sp.n[1] = (int)n1;
+  std::memcpy(sp.b[0], src0, n0);
+  std::memcpy(sp.b[1], src1, n1);
+  hipLaunchKernelGGL(store_pair_kernel, dim3(1), dim3(64), 0, st, sp);
+  return hipGetLastError();
 }
 
 // Tile layout <-> canonical layouts, one thread per (pixel, class).

@@ -60,8 +60,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   const bool g4s = VAR && a.g4s;
   const gptr<const T> gz = glob(a.z);
   const gptr<const T> gphat = glob(a.phat);
+  const gptr<const T> gdm_in = glob(a.dm_in);
+  const gptr<const T> gd2_in = glob(a.d2_in);   // (h, v) pairs
   const gptr<T> gdm = glob(a.dm);
-  const gptr<T> gd2 = glob(a.d2);   // (h, v) pairs
+  const gptr<T> gd2 = glob(a.d2);
 
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
@@ -122,10 +124,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     if (k < K && vn) {
       const size_t kb = ((size_t)tile * g.steps + sn) * K + k;
       Pp[kk] = gphat[kb * 64 + lane];
-      P1[kk] = gdm[(kb * 3 + 0) * 64 + lane];
-      P3[kk] = gdm[(kb * 3 + 1) * 64 + lane];
-      P4[kk] = gdm[(kb * 3 + 2) * 64 + lane];
-      const gptr<T> d2p = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
+      P1[kk] = gdm_in[(kb * 3 + 0) * 64 + lane];
+      P3[kk] = gdm_in[(kb * 3 + 1) * 64 + lane];
+      P4[kk] = gdm_in[(kb * 3 + 2) * 64 + lane];
+      const gptr<const T> d2p = gd2_in + 2 * (kb * (size_t)(L * 64) + lane);
 #pragma unroll
       for (int j = 0; j < LP; ++j) {
         Pd[kk][j][0] = d2p[j * 128];
@@ -161,9 +163,9 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
           d4 = P4[kk];
         } else {
           pk[kk] = gphat[kb * 64 + lane];
-          d1 = gdm[(kb * 3 + 0) * 64 + lane];
-          d3 = gdm[(kb * 3 + 1) * 64 + lane];
-          d4 = gdm[(kb * 3 + 2) * 64 + lane];
+          d1 = gdm_in[(kb * 3 + 0) * 64 + lane];
+          d3 = gdm_in[(kb * 3 + 1) * 64 + lane];
+          d4 = gdm_in[(kb * 3 + 2) * 64 + lane];
         }
         const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
         const T zc = zk[0];
@@ -174,7 +176,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         pq += pk[kk] * pk[kk];
         psv += v4[kk];
         if (g4s) v4buf[((s & 1) * K + k) * 64 + lane] = v4[kk];
-        const gptr<T> d2p = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
+        const gptr<const T> d2p = gd2_in + 2 * (kb * (size_t)(L * 64) + lane);
 #pragma unroll
         for (int j = 0; j < L; ++j) {
           const int dy = j / D - M, dx = j % D - M;

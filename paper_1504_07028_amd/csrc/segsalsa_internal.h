@@ -182,8 +182,13 @@ struct ProxArgs {
   int nw;                     // wavefronts per workgroup
   const T* __restrict__ z;    // [K][H][W]
   const T* __restrict__ phat; // tile layout
-  T* __restrict__ dm;
-  T* __restrict__ d2;
+  // multipliers of the round's input state (d1, d3, d4 and d2, tile layout)
+  // and where the updated ones go: the same arrays for an update in place,
+  // another state's for rounds that keep every state (the reverse sweep)
+  const T* dm_in;
+  const T* d2_in;
+  T* dm;
+  T* d2;
   T* __restrict__ acc;
   double* __restrict__ res_tile;  // non-null on checked rounds: per-tile sum of (d_new - d_old)^2
   double mu, tau;

@@ -126,6 +126,10 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 // Copy n host bytes into device memory through kernel arguments (no host
 // staging buffer has to outlive the call; capturable in a graph).
 hipError_t launch_store(void* dst, const void* src, size_t n, hipStream_t st);
+// Two such stores of at most kStorePairMax bytes each in one launch.
+constexpr int kStorePairMax = 64;
+hipError_t launch_store_pair(void* dst0, const void* src0, size_t n0, void* dst1, const void* src1, size_t n1,
+                             hipStream_t st);
 
 // Conversion between the tile layout and canonical class-planar arrays.
 template <typename T>

@@ -107,6 +107,8 @@ def lib():
     L.segsalsa_str_solve_batch.restype = c_int32
     L.segsalsa_str_grad_workspace_size.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, POINTER(c_size_t)]
     L.segsalsa_str_grad_workspace_size.restype = c_int32
+    L.segsalsa_str_grad_checkpoint_interval.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, POINTER(c_int32)]
+    L.segsalsa_str_grad_checkpoint_interval.restype = c_int32
     L.segsalsa_str_solve_ckpt.argtypes = [POINTER(segsalsa_problem), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                                           c_size_t, c_void_p]
     L.segsalsa_str_solve_ckpt.restype = c_int32
@@ -327,6 +329,15 @@ def segsalsa_str_grad_workspace_size(problem: Problem, precision: int, checkpoin
     return int(n.value)
 
 
+def segsalsa_str_grad_checkpoint_interval(problem: Problem, precision: int, checkpoint_every: int = 0) -> int:
+    """The checkpoint interval S that checkpoint_every (0 = automatic) resolves to."""
+    n = c_int32(0)
+    s = problem.c_struct()
+    _check(lib().segsalsa_str_grad_checkpoint_interval(ctypes.byref(s), int(precision), int(checkpoint_every),
+                                                       ctypes.byref(n)))
+    return int(n.value)
+
+
 def segsalsa_str_solve_ckpt(problem: Problem, checkpoint_every: int, inp, z_out, workspace, stream=None):
     nel = problem.K * problem.H * problem.W
     s = problem.c_struct()
@@ -412,12 +423,13 @@ class SegSalsaSTR(torch.autograd.Function):
 
     apply(inp, lam, weights, patch_radius, schatten_p, mu, iters, input_is_logits, checkpoint_every)
     inp: device tensor [K][H][W]; lam: 0-d tensor or float; weights: tensor or list of L multipliers.
-    The forward keeps checkpoints in a workspace saved for the backward, which calls the reverse sweep.
+    The forward keeps checkpoints in a workspace saved for the backward, which calls the reverse sweep;
+    checkpoint_every = 0 lets the library pick the interval (every state where they fit in 8 GiB).
     """
 
     @staticmethod
     def forward(ctx, inp, lam, weights, patch_radius, schatten_p=1.0, mu=1.0, iters=100, input_is_logits=False,
-                checkpoint_every=10):
+                checkpoint_every=0):
         inp = inp.contiguous()
         K, H, W = inp.shape
         lam_f = float(lam)

@@ -152,7 +152,8 @@ def test_grad_workspace_size_and_restrictions(S):
     assert grad_size(S, base_problem(S, iters=20), 1)[1] > base
     assert grad_size(S, base_problem(S, iters=20), 5)[1] < base
     assert grad_size(S, base_problem(S, iters=0), 10)[0] == OK
-    assert grad_size(S, base_problem(S), 0)[0] == INVALID
+    assert grad_size(S, base_problem(S), -1)[0] == INVALID
+    assert grad_size(S, base_problem(S, iters=20), 0) == grad_size(S, base_problem(S, iters=20), 1)   # auto: all
     assert grad_size(S, base_problem(S, residual_every=2), 5)[0] == UNSUPPORTED
     assert grad_size(S, base_problem(S, residual_every=2, tol=1e-3), 5)[0] == UNSUPPORTED
     assert grad_size(S, base_problem(S, warm_start=True), 5)[0] == UNSUPPORTED
@@ -189,7 +190,30 @@ def test_grad_argument_errors_before_launch(S):
     assert bwd(fin, fg, fg, None, None, fws, need) == INVALID          # grad_input aliases grad_z
     assert bwd(fin, fg, fgi, 0x600004, None, fws, need) == INVALID     # misaligned grad_lambda
     assert bwd(fin, fg, fgi, None, None, fws, need - 1) == WORKSPACE
-    assert bwd(fin, fg, fgi, None, None, fws, need, ck=0) == INVALID
+    assert bwd(fin, fg, fgi, None, None, fws, need, ck=-1) == INVALID
+
+
+def test_checkpoint_interval(S):
+    """checkpoint_every = 0 keeps every state while they fit in 8 GiB, else the smallest interval that fits
+    (ceil(N / S) checkpoints plus S - 1 recomputed states), else ceil(sqrt(N)); other values are clamped to
+    [1, iters]."""
+    pr = base_problem(S)
+    assert S.segsalsa_str_grad_checkpoint_interval(pr, 1, 0) == 1
+    assert S.segsalsa_str_grad_checkpoint_interval(pr, 1, 2) == 2
+    assert S.segsalsa_str_grad_checkpoint_interval(pr, 1, 10 ** 6) == max(1, pr.iters)
+    # 2048 x 2048, K = 16, 5x5 patch, FP32: one state is (4 + 2L) K n words = 54 * 16 * 4 Mi * 4 B = 13.5 GiB,
+    # more than the budget even alone, so ceil(sqrt(500)) = 23
+    big = S.Problem(16, 2048, 2048, 2, [0.2] * 25, 1.0, 1.0, 1.0, 500)
+    assert S.segsalsa_str_grad_checkpoint_interval(big, 0, 0) == 23
+    # 256 x 256, K = 8, 3x3, FP32, 50 rounds: 46 MB a state, all 51 fit
+    mid = S.Problem(8, 256, 256, 1, [1.0 / 3] * 9, 1.0, 1.0, 1.0, 50)
+    assert S.segsalsa_str_grad_checkpoint_interval(mid, 0, 0) == 1
+    # 1024 x 1024, K = 16, 3x3, FP32, 200 rounds: 1.4 GiB a state; 8 GiB holds 5 of them, and
+    # ceil(200 / S) + S - 1 <= 5 has no solution, so ceil(sqrt(200)) = 15
+    lg = S.Problem(16, 1024, 1024, 1, [1.0 / 3] * 9, 1.0, 1.0, 1.0, 200)
+    assert S.segsalsa_str_grad_checkpoint_interval(lg, 0, 0) == 15
+    with pytest.raises(RuntimeError):
+        S.segsalsa_str_grad_checkpoint_interval(pr, 1, -1)
 
 
 def test_g4_simplex_flag(S):
@@ -311,7 +335,10 @@ def test_shipped_cache_is_read(S):
     assert loaded == len(entries) and skipped == 0
     for e in entries:
         got, tuned = S.segsalsa_tuning_get(e["K"], e["H"], e["W"], e["M"], 1 if e["precision"] == "fp64" else 0)
-        assert tuned and got["tile_rows"] == e["tile_rows"] and got["col_threads"] == e["col_threads"]
+        assert tuned
+        # fields the entry leaves at 0 (threads of the power-of-two FFT kernels) are filled in by the planner
+        for f in S.TUNING_FIELDS[:-1]:
+            assert e[f] == 0 or got[f] == e[f], (e, f, got[f])
 
 
 def test_autotune_argument_errors(S):

@@ -103,3 +103,30 @@ def test_prefetching_prox_build_matches_oracle(table, case):
                                                              tile_cols=16))
     z2, _, _, _ = gpu_solve(S, probs, c, M, 1.0, 0.8, 1.1, iters, torch.float32)
     assert torch.equal(z, z2)
+
+
+def test_batch_of_several_images_ignores_table(table):
+    """Batches of more than one image keep the planner's shapes: an entry for one of their shapes
+    leaves the batch's z bit for bit as it was, while a solve of that image alone takes it."""
+    S = table
+    from test_gpu_batch import make_inputs, run_batch, run_single
+    import synth
+    shapes = [(37, 53, 4), (61, 29, 9)]
+    M, p, iters = 1, 1.0, 6
+    c = synth.gaussian_patch_multipliers(M, 1.0)
+    probs = make_inputs(shapes, 400)
+    lams, mus = [0.7, 0.9], [1.1, 1.2]
+    ref, _, _ = run_batch(S, shapes, probs, c, M, p, lams, mus, iters, torch.float32)
+    ref = [t.clone() for t in ref]
+    H, W, K = shapes[0]
+    S.segsalsa_tuning_set(K, H, W, M, S.SEGSALSA_FP32, dict(tile_rows=3, tile_cols=7, classes_per_wave=1,
+                                                          rows_per_block=1, row_threads=64))
+    got, _, _ = run_batch(S, shapes, probs, c, M, p, lams, mus, iters, torch.float32)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    zs, _ = run_single(S, probs[0], c, M, p, lams[0], mus[0], iters, torch.float32)
+    zo = oracle_solve(rounded_input(probs[0], torch.float32), weights_as_seen(c, torch.float32), M, p, lams[0], mus[0],
+                      iters)
+    err = float(np.max(np.abs(zs.double().cpu().numpy() - zo)))
+    say(f"  tuned single solve: max |z - z_oracle| = {err:.3e}")
+    check_err(err, torch.float32)
