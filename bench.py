@@ -240,18 +240,9 @@ def bench_sweep(S, torch, synth, wl_name="pines_145x145_k16", radii=(0, 1, 2, 3,
     return out
 
 
-def plan_record(S, K, H, W, M, prec, batch=False):
-    """The launch shapes of one image shape; batch=True: those of an image inside a batch of several,
-    which keeps the planner's shapes even where the tuning table has an entry."""
+def plan_record(S, K, H, W, M, prec):
+    """The launch shapes of a single-image solve of this shape and whether they came from the tuning table."""
     t, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
-    if batch and tuned:
-        entry = t
-        S.segsalsa_tuning_set(K, H, W, M, prec, None)
-        try:
-            t, _ = S.segsalsa_tuning_get(K, H, W, M, prec)
-        finally:
-            S.segsalsa_tuning_set(K, H, W, M, prec, entry)
-        tuned = False
     rec = {k: v for k, v in t.items() if k != "us_per_round"}
     rec["tuned"] = tuned
     return rec
@@ -303,8 +294,9 @@ def bench_batch(S, torch, synth, steps, warmup, fp32_only=False, graph=True):
            "round_roofline": round_roofline(n_units, L, round_us),
            "z_err_fp32_vs_fp64": z_err,
            "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in out["f32"]["phases"].items()},
-           "plans": [dict(K=K, H=H, W=W, **plan_record(S, K, H, W, B["M"], S.SEGSALSA_FP32, batch=True))
-                     for (H, W, K) in shapes]}
+           "plans": [dict(K=K, H=H, W=W, **{k: v for k, v in t.items() if k != "us_per_round"}, tuned=False)
+                     for (H, W, K), t in zip(shapes, S.segsalsa_str_batch_plans(
+                         imgs, S.BatchParams(B["M"], c, 1.0, B["iters"]), S.SEGSALSA_FP32))]}
     if "f64" in out:
         res["fp64"] = {"value": out["f64"]["value"], "ms_per_step": out["f64"]["ms_per_step"]}
         res["speedup_fp32_vs_fp64"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]

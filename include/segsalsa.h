@@ -215,7 +215,11 @@ segsalsa_status segsalsa_str_batch_workspace_size(int32_t n_images, const segsal
  *   input_packed   device buffer holding every image's input at its in_offset.
  *   z_packed       device buffer receiving every image's z at its out_offset.
  *   stats          HOST, n_images entries or NULL (required with residuals).
- * The result of each image equals segsalsa_str_solve on that image alone.
+ * The result of each image equals, bit for bit, segsalsa_str_solve on that
+ * image alone when the tuning table has no entry for its shape (the batch
+ * keeps the planner's tiles; its FFT blocking depends on the transform
+ * length only, so that images of one length share a launch, and does not
+ * change the arithmetic); with an entry, the single solve agrees to rounding.
  */
 segsalsa_status segsalsa_str_solve_batch(int32_t n_images, const segsalsa_image *images,
                                          const segsalsa_batch_params *params, segsalsa_precision precision,
@@ -313,10 +317,12 @@ typedef struct {
   int32_t classes_per_wave;      /* classes per wavefront of the prox kernel: 1, 2 or 4, or 0          */
   int32_t prefetch;              /* 1: the prox kernel build that loads step s + 1 while step s
                                     updates (FP32, classes_per_wave = 2, patch radius <= 2); 0: not    */
-  int32_t generic_fft;           /* 1: the general mixed-radix FFT kernels also for power-of-two sides
-                                    (64 .. 4096), which otherwise take the fixed-structure kernels with
-                                    N / 16 threads per transform (their threads are then rows or
-                                    columns per block times N / 16)                                    */
+  int32_t generic_fft;           /* 1: the general mixed-radix FFT kernels (Bluestein in LDS) also for
+                                    the sides that otherwise take the fixed-structure engine: powers of
+                                    two 64 .. 4096 (N / 16 threads per transform) and sides taking
+                                    Bluestein with a convolution length M of 64 .. 4096 (M / 16 threads
+                                    per transform); with the engine, threads are rows or columns per
+                                    block times N / 16 or M / 16                                       */
   int32_t rows_per_block;        /* rows per workgroup of the row DFT passes (> 0), or 0               */
   int32_t row_threads;           /* threads per row workgroup, a multiple of 64 in [64, 1024], or 0    */
   int32_t cols_per_block;        /* columns per workgroup of the column pass (> 0), or 0               */
@@ -343,6 +349,14 @@ segsalsa_status segsalsa_tuning_load(const char *path, int32_t *loaded /* HOST, 
                                      int32_t *skipped /* HOST, may be NULL */);
 /* Write the whole table as a JSON tuning cache. */
 segsalsa_status segsalsa_tuning_save(const char *path);
+
+/* The launch shapes each image of this batch runs with (not part of the
+ * method): plans[i] (HOST, n_images entries) receives image i's prox tile,
+ * classes per wavefront and FFT blocking, as segsalsa_tuning_get reports them
+ * for single images (us_per_round = 0). */
+segsalsa_status segsalsa_str_batch_plans(int32_t n_images, const segsalsa_image *images,
+                                         const segsalsa_batch_params *params, segsalsa_precision precision,
+                                         segsalsa_tuning *plans /* HOST, out */);
 
 /*
  * Measure launch shapes for `prob`'s image shape on the device and store the

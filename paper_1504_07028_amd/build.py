@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsegsalsa.so")
-SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "fft_pow2_kernels.hip", "misc_kernels.hip",
+SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "fft_pow2_kernels.hip", "fft_blu_kernels.hip",
+           "misc_kernels.hip",
            "residual_kernels.hip", "adjoint_kernels.hip"]
 ARCH = "gfx950"
 
@@ -38,7 +39,7 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libsegsalsa.so; returns its path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -30,7 +30,7 @@
 namespace segsalsa {
 
 template <typename T, int M, int KPW>
-__global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kernel(const AdjArgs<T> a) {
+__global__ void __launch_bounds__((adj_max_threads<T, M, KPW>()), (adj_min_waves<T, M, KPW>())) adj_prox_kernel(const AdjArgs<T> a) {
   constexpr int D = 2 * M + 1;
   constexpr int L = D * D;
   constexpr int NS = 10;  // cross-class sums per pixel
@@ -89,10 +89,15 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
 
   const int P = th * tw;
   const int nsteps = (P + 63) >> 6;
-  double cb[L];
+  // per-lane parameter sums over the tile's pixels and the wavefront's
+  // classes: FP64 for FP64, FP32 for FP32 (a few dozen terms per lane,
+  // reduced across lanes and tiles in FP64; half the registers)
+  using Acc = typename std::conditional<sizeof(T) == 4, float, double>::type;
+  Acc cb[L];
 #pragma unroll
-  for (int j = 0; j < L; ++j) cb[j] = 0.0;
-  double wb = 0.0, lb = 0.0;
+  for (int j = 0; j < L; ++j) cb[j] = Acc(0);
+  Acc wb = Acc(0);
+  double lb = 0.0;
   for (int s = 0; s < nsteps; ++s) {
     const int f = (s << 6) + lane;
     const bool valid = f < P;
@@ -165,7 +170,11 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
       tot[q * 64 + lane] = t;
     }
     __syncthreads();
-    const int wn = nw > 1 ? 1 : 0;  // the two closed forms on two wavefronts (register peak)
+    // the closed forms on three wavefronts: g1 and its derivatives, the
+    // Schatten multiplier N, and its vector-Jacobian product (each recomputes
+    // the eigenvalues; in parallel the FP64 phase is as long as its longest part)
+    const int wn = nw > 1 ? 1 : 0;
+    const int wv = nw > 2 ? 2 : wn;
     if (wid == 0 && valid) {
       const double S = tot[0 * 64 + lane], Q = tot[1 * 64 + lane], PU = tot[2 * 64 + lane];
       // g1: gain and its partial derivatives in s = p^T v and q = ||p||^2
@@ -178,17 +187,19 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
       coef[2 * 64 + lane] = 2.0 * gq * PU;
       coef[3 * 64 + lane] = tot[3 * 64 + lane] / (double)K;
     }
-    if (wid == wn && valid) {
-      const double A = tot[4 * 64 + lane], B = tot[5 * 64 + lane], C = tot[6 * 64 + lane];
-      // g2: multiplier N and the cotangent of S
-      double n11, n12, n22, s11, s12, s22, dtau;
-      schatten_multiplier<false>(A, B, C, a.tau, a.pkind, 0.0, n11, n12, n22);
-      schatten_multiplier_vjp(A, B, C, a.tau, a.pkind, tot[7 * 64 + lane], 0.5 * tot[8 * 64 + lane],
-                              tot[9 * 64 + lane], s11, s12, s22, dtau);
-      lb += dtau;
+    if (wid == wn && valid) {  // g2: multiplier N
+      double n11, n12, n22;
+      schatten_multiplier<false>(tot[4 * 64 + lane], tot[5 * 64 + lane], tot[6 * 64 + lane], a.tau, a.pkind, 0.0,
+                                 n11, n12, n22);
       coef[4 * 64 + lane] = n11;
       coef[5 * 64 + lane] = n12;
       coef[6 * 64 + lane] = n22;
+    }
+    if (wid == wv && valid) {  // g2: the cotangent of S and of tau
+      double s11, s12, s22, dtau;
+      schatten_multiplier_vjp(tot[4 * 64 + lane], tot[5 * 64 + lane], tot[6 * 64 + lane], a.tau, a.pkind,
+                              tot[7 * 64 + lane], 0.5 * tot[8 * 64 + lane], tot[9 * 64 + lane], s11, s12, s22, dtau);
+      lb += dtau;
       coef[7 * 64 + lane] = 2.0 * s11;
       coef[8 * 64 + lane] = 2.0 * s12;
       coef[9 * 64 + lane] = 2.0 * s22;
@@ -227,8 +238,7 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
           {  // <D rb, D z'> at this pixel and class (the Wsum term of A)
             const T* zn = a.zn + (size_t)k * H * W;
             const T znc = zn[ic];
-            wb += (double)(rk[1] - rk[0]) * (double)(zn[irr] - znc) +
-                  (double)(rk[EC] - rk[0]) * (double)(zn[idn] - znc);
+            wb += (Acc)(rk[1] - rk[0]) * (Acc)(zn[irr] - znc) + (Acc)(rk[EC] - rk[0]) * (Acc)(zn[idn] - znc);
           }
           C2<T>* b2p = reinterpret_cast<C2<T>*>(a.bd2) + kb * (size_t)(L * 64) + lane;
           // Cotangent of Y per offset and its J^T scatter, destinations walked
@@ -262,8 +272,8 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
                 b2p[jj * 64] = o;
                 const T a2h = T(2) * (yh * m11 + yv * m12) - yh;
                 const T a2v = T(2) * (yh * m12 + yv * m22) - yv;
-                cb[jj] += (double)ybh * (double)gzh + (double)ybv * (double)gzv + (double)grh * (double)a2h +
-                          (double)grv * (double)a2v;
+                cb[jj] += (Acc)ybh * (Acc)gzh + (Acc)ybv * (Acc)gzv + (Acc)grh * (Acc)a2h +
+                          (Acc)grv * (Acc)a2v;
                 ah = a.c[jj] * ybh;
                 av = a.c[jj] * ybv;
               }
@@ -299,7 +309,7 @@ __global__ void __launch_bounds__((adj_max_threads<T, M, KPW>())) adj_prox_kerne
   double* red = reinterpret_cast<double*>(part);
   constexpr int NQ = L + 2;
   for (int q = 0; q < NQ; ++q) {
-    double v = q < L ? cb[q] : (q == L ? lb : wb);
+    double v = q < L ? (double)cb[q] : (q == L ? lb : (double)wb);
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if (lane == 0) red[q * nw + wid] = v;
   }

@@ -99,6 +99,13 @@ FftPlanDev make_fft_plan(int N) {
   return p;
 }
 
+// Lengths the fixed-structure engine runs: powers of two 64 .. 4096, and
+// lengths taking Bluestein whose convolution length is in that range.
+bool engine_length(int n) {
+  const FftPlanDev f = make_fft_plan(n);
+  return f.blu ? p2_length(f.M) : p2_length(n);
+}
+
 struct Plan {
   bool fp64;
   size_t ts;     // sizeof(T)
@@ -113,7 +120,8 @@ struct Plan {
   FftPlanDev frow, fcol;
   // FFT workgroups: transforms per workgroup, threads, elements per thread
   int rows_per_block, row_threads, row_ept;
-  int row_p2, col_p2;   // power-of-two length of the fixed-structure row (column) kernels, 0: general kernels
+  int row_p2, col_p2;   // length of the fixed-structure row (column) engine, 0: general kernels
+  bool row_blu, col_blu;   // the engine runs the Bluestein convolution (its length is frow.M / fcol.M)
   size_t row_lds;
   int cols_per_block, col_threads, col_ept;
   size_t col_lds;
@@ -336,7 +344,13 @@ segsalsa_status validate_problem(const segsalsa_problem* pr, segsalsa_precision 
 // Per-image plan: tile grid, FFT factorisations and launch shapes, and the
 // layout of the image's region of the workspace (offsets from its base).
 // ---------------------------------------------------------------------------
-segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_tuning& tn, Plan& p) {
+// batch: the image is one of several solved together; the FFT blocking that
+// the tuning entry leaves open then depends only on the transform length
+// (rows or columns per workgroup, threads and elements per thread), not on
+// how many workgroups the image alone would fill, so that the images of
+// one length share a launch.
+segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_tuning& tn, Plan& p,
+                          bool batch = false) {
   p.fp64 = c.fp64;
   p.ts = c.ts;
   p.K = K; p.H = H; p.W = W; p.M = c.M;
@@ -396,10 +410,14 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   const size_t cs = 2 * p.ts;
   p.frow = make_fft_plan(W);
   p.fcol = make_fft_plan(H);
-  // Bluestein needs scratch next to the data; where that exceeds LDS, keep
-  // the direct stages
-  if (p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
-  if (p.fcol.blu && ((size_t)H + p.fcol.M) * cs > kLdsBudget) p.fcol.blu = 0;
+  // Bluestein lengths of 64 .. 4096 run their convolution FFTs on the
+  // fixed-structure engine (unless the general kernels are asked for)
+  p.row_blu = p.frow.blu && p2_length(p.frow.M) && !tn.generic_fft;
+  p.col_blu = p.fcol.blu && p2_length(p.fcol.M) && !tn.generic_fft;
+  // the general kernels' Bluestein needs scratch next to the data; where
+  // that exceeds LDS, keep the direct stages
+  if (!p.row_blu && p.frow.blu && ((size_t)W + p.frow.M) * cs > kLdsBudget) p.frow.blu = 0;
+  if (!p.col_blu && p.fcol.blu && ((size_t)H + p.fcol.M) * cs > kLdsBudget) p.fcol.blu = 0;
   // FFT workgroups.  Rows: whole rows plus the twiddle table (or the
   // Bluestein scratch) in LDS, about 2048 (FP32) / 1024 (FP64) elements per
   // workgroup at about 8 per thread (a radix-8 stage then keeps every thread
@@ -411,19 +429,21 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   // whose transform structure is fixed at compile time: N / 16 threads per
   // transform, about 256 threads per row workgroup and 512 per column
   // workgroup (FP64: 256), each transform in its own padded LDS region.
+  // Bluestein lengths take the same engine over their convolution length M.
   const int maxthr_p2 = p.fp64 ? kFftNarrowThreads : kFftMaxThreads;
-  p.row_p2 = !p.frow.blu && p2_length(W) && !tn.generic_fft ? W : 0;
-  p.col_p2 = !p.fcol.blu && p2_length(H) && !tn.generic_fft ? H : 0;
+  p.row_p2 = p.row_blu ? p.frow.M : (!p.frow.blu && p2_length(W) && !tn.generic_fft ? W : 0);
+  p.col_p2 = p.col_blu ? p.fcol.M : (!p.fcol.blu && p2_length(H) && !tn.generic_fft ? H : 0);
   if (p.row_p2) {
-    const int tpt = W / 16;
+    const int tpt = p.row_p2 / 16;
     // default: about 256 threads, at least one wavefront, and two workgroups per CU when the image has the rows
-    long long rpb = tn.rows_per_block > 0
-                        ? std::min<long long>(tn.rows_per_block, H)
-                        : std::min<long long>(H, std::max<long long>(std::max(1, 64 / tpt),
-                                                                     std::min<long long>(256 / tpt, (long long)p.P * H /
-                                                                                                        (2 * kTargetGroups))));
+    long long rpb = tn.rows_per_block > 0 ? std::min<long long>(tn.rows_per_block, H)
+                    : batch             ? std::max(1, 256 / tpt)
+                                        : std::min<long long>(H, std::max<long long>(std::max(1, 64 / tpt),
+                                                                                    std::min<long long>(256 / tpt,
+                                                                                                        (long long)p.P * H /
+                                                                                                            (2 * kTargetGroups))));
     const long long thr = rpb * tpt;
-    const size_t lds = (size_t)rpb * p2_region(W) * cs;
+    const size_t lds = (size_t)rpb * p2_region(p.row_p2) * cs;
     if (thr > maxthr_p2 || lds > kLdsBudget || (tn.row_threads > 0 && tn.row_threads != thr))
       return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld rows of %d per workgroup (%lld threads, %zu bytes of LDS) do not fit",
                   rpb, W, thr, lds);
@@ -438,19 +458,22 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     };
     const long long nrows = (long long)p.P * H;
     long long rpb;
+    const int rbudget = p.fp64 ? 1024 : 2048;   // elements per workgroup
     if (tn.rows_per_block > 0) {
       rpb = std::min<long long>(tn.rows_per_block, H);
     } else {
-      rpb = std::max<long long>(1, (p.fp64 ? 1024 : 2048) / Lr);
-      rpb = std::min<long long>(rpb, std::max<long long>(1, nrows / (2 * kTargetGroups)));
+      rpb = std::max<long long>(1, rbudget / Lr);
+      if (!batch) rpb = std::min<long long>(rpb, std::max<long long>(1, nrows / (2 * kTargetGroups)));
       rpb = std::max<long long>(1, std::min<long long>(rpb, H));
       while (rpb > 1 && (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads || lds_of(rpb) > kLdsBudget)) --rpb;
     }
     if (rpb * Lr > (long long)kFftEptMax * kFftMaxThreads || lds_of(rpb) > kLdsBudget)
       return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld rows of %d per FFT workgroup do not fit", rpb, W);
     const long long items = rpb * Lr;
-    int thr = tn.row_threads > 0 ? tn.row_threads : fft_threads_for(items, 8);
-    int ept = fft_ept(items, thr);
+    // in a batch, every row workgroup that holds the budget has the same shape
+    const bool uniform = batch && tn.row_threads <= 0 && items <= rbudget;
+    int thr = tn.row_threads > 0 ? tn.row_threads : uniform ? rbudget / 8 : fft_threads_for(items, 8);
+    int ept = uniform ? 8 : fft_ept(items, thr);
     if (ept == 0) {
       if (tn.row_threads > 0)
         return fail(SEGSALSA_ERR_UNSUPPORTED, "%d row threads hold at most 16 of %lld elements each", thr, items);
@@ -463,17 +486,18 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     p.row_lds = lds_of(rpb);
   }
   if (p.col_p2) {
-    const int tpt = H / 16;
+    const int tpt = p.col_p2 / 16;
     // default: about 512 threads (FP64: 256), at least one wavefront, one workgroup per CU when there are the columns
-    long long cb = tn.cols_per_block > 0
-                       ? std::min<long long>(tn.cols_per_block, W)
-                       : std::min<long long>(W, std::max<long long>(std::max(1, 64 / tpt),
-                                                                    std::min<long long>((p.fp64 ? 256 : 512) / tpt,
-                                                                                        (long long)p.P * W /
-                                                                                            kTargetGroups)));
+    long long cb = tn.cols_per_block > 0 ? std::min<long long>(tn.cols_per_block, W)
+                   : batch               ? std::max(1, (p.fp64 ? 256 : 512) / tpt)
+                                         : std::min<long long>(W, std::max<long long>(std::max(1, 64 / tpt),
+                                                                                     std::min<long long>((p.fp64 ? 256 : 512) / tpt,
+                                                                                                         (long long)p.P * W /
+                                                                                                             kTargetGroups)));
     const long long thr = cb * tpt;
-    const size_t lds = (size_t)cb * p2_region(H) * cs;
-    if (thr > maxthr_p2 || lds > kLdsBudget || (tn.col_threads > 0 && tn.col_threads != thr))
+    const size_t lds = (size_t)cb * p2_region(p.col_p2) * cs;
+    const int maxthr_col = p.col_blu ? kFftNarrowThreads : maxthr_p2;   // the Bluestein column kernel's bound
+    if (thr > maxthr_col || lds > kLdsBudget || (tn.col_threads > 0 && tn.col_threads != thr))
       return fail(SEGSALSA_ERR_UNSUPPORTED,
                   "%lld columns of %d per workgroup (%lld threads, %zu bytes of LDS) do not fit", cb, H, thr, lds);
     p.cols_per_block = (int)cb;
@@ -486,21 +510,24 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
       return ((size_t)cb * H + (p.fcol.blu ? (size_t)cb * Lc : (size_t)H)) * cs;
     };
     long long cb;
+    const int cbudget = 4096;   // elements per workgroup of a batch's uniform column shape
     if (tn.cols_per_block > 0) {
       cb = std::min<long long>(tn.cols_per_block, W);
     } else {
       cb = 1;
       const long long cmax = p.fp64 ? 8 : 16;   // 128-byte runs
       while (cb * 2 <= cmax && cb * 2 <= W && lds_of(cb * 2) <= 80 * 1024 &&
-             cb * 2 * Lc <= (long long)kFftEptMax * kFftMaxThreads &&
-             (long long)p.P * ceil_div(W, (int)(cb * 2)) >= kTargetGroups)
+             cb * 2 * Lc <= (batch ? cbudget : (long long)kFftEptMax * kFftMaxThreads) &&
+             (batch || (long long)p.P * ceil_div(W, (int)(cb * 2)) >= kTargetGroups))
         cb *= 2;
     }
     if (cb * Lc > (long long)kFftEptMax * kFftMaxThreads || lds_of(cb) > kLdsBudget)
       return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld columns of %d per FFT workgroup do not fit", cb, H);
     const long long items = cb * Lc;
-    int thr = tn.col_threads > 0 ? tn.col_threads : fft_threads_for(items, 8);
-    int ept = fft_ept(items, thr);
+    // in a batch, every column workgroup within the budget has the same shape
+    const bool uniform = batch && tn.col_threads <= 0 && items <= cbudget;
+    int thr = tn.col_threads > 0 ? tn.col_threads : uniform ? cbudget / 8 : fft_threads_for(items, 8);
+    int ept = uniform ? 8 : fft_ept(items, thr);
     if (ept == 0) {
       if (tn.col_threads > 0)
         return fail(SEGSALSA_ERR_UNSUPPORTED, "%d column threads hold at most 16 of %lld elements each", thr, items);
@@ -548,25 +575,26 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
 // differentiable solve sizes its tiles for the reverse sweep too, and the
 // simplex g4 needs more LDS), else the planner's own choices.  The entries
 // are measured with the image alone on the device; the images of a batch
-// share it, and the planner's shapes (sized on each image's own work) group
-// into fewer, fuller launches there.
+// share it, and take the planner's batch shapes (FFT blocking by transform
+// length only), which group into few, full launches.
 void log_plan(const Plan& p) {
   const int K = p.K, H = p.H, W = p.W;
   if (const char* lg = std::getenv("SEGSALSA_LOG")) {
     if (lg[0] == '1')
       std::fprintf(stderr,
                    "[segsalsa] plan %s K=%d H=%d W=%d M=%d%s: tiles %dx%d (max %dx%d, %d tiles, %d steps), prox nw=%d "
-                   "kpw=%d%s lds=%zu; rows/block=%d threads=%d ept=%d lds=%zu; cols/block=%d threads=%d ept=%d "
-                   "lds=%zu; region %zu B\n",
+                   "kpw=%d%s lds=%zu; rows/block=%d threads=%d ept=%d engine=%d%s lds=%zu; cols/block=%d "
+                   "threads=%d ept=%d engine=%d%s lds=%zu; region %zu B\n",
                    p.fp64 ? "fp64" : "fp32", K, H, W, p.M, p.tuned ? " (tuned)" : "", p.g.ntr, p.g.ntc, p.g.TR,
-                   p.g.TC, p.g.ntiles(), p.g.steps, p.nw, p.kpw, p.pf ? " prefetch" : "", p.prox_lds, p.rows_per_block, p.row_threads,
-                   p.row_ept, p.row_lds, p.cols_per_block, p.col_threads, p.col_ept, p.col_lds, p.total);
+                   p.g.TC, p.g.ntiles(), p.g.steps, p.nw, p.kpw, p.pf ? " prefetch" : "", p.prox_lds, p.rows_per_block,
+                   p.row_threads, p.row_ept, p.row_p2, p.row_blu ? " bluestein" : "", p.row_lds, p.cols_per_block,
+                   p.col_threads, p.col_ept, p.col_p2, p.col_blu ? " bluestein" : "", p.col_lds, p.total);
   }
 }
 
-segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p, bool use_table = true) {
+segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p, bool batch = false) {
   segsalsa_tuning tn{};
-  if (use_table && !c.grad && tuning_lookup(K, H, W, c.M, c.fp64, tn)) {
+  if (!batch && !c.grad && tuning_lookup(K, H, W, c.M, c.fp64, tn)) {
     const std::string saved = g_last_error;
     if (plan_with(K, H, W, c, tn, p) == SEGSALSA_OK) {
       p.tuned = true;
@@ -575,7 +603,7 @@ segsalsa_status make_image_plan(int K, int H, int W, const Common& c, Plan& p, b
     }
     g_last_error = saved;
   }
-  segsalsa_status s = plan_with(K, H, W, c, segsalsa_tuning{}, p);
+  segsalsa_status s = plan_with(K, H, W, c, segsalsa_tuning{}, p, batch);
   if (s == SEGSALSA_OK) log_plan(p);
   return s;
 }
@@ -687,7 +715,7 @@ segsalsa_status make_batch(int n, const int* K, const int* H, const int* W, cons
     segsalsa_status s = validate_image(K[i], H[i], W[i], lam[i], mu[i]);
     if (s != SEGSALSA_OK) return fail(s, "image %d: %s", i, segsalsa_last_error());
     s = force ? plan_with(K[i], H[i], W[i], c, *force, b.im[i].plan)
-              : make_image_plan(K[i], H[i], W[i], c, b.im[i].plan, n == 1);
+              : make_image_plan(K[i], H[i], W[i], c, b.im[i].plan, n > 1);
     if (s != SEGSALSA_OK) return s;
     b.im[i].base = off;
     b.im[i].lambda = lam[i];
@@ -715,7 +743,8 @@ struct LaunchSet {
   struct FftGroup {
     int ept, threads, first, count, blocks;
     size_t lds;
-    int p2;   // power-of-two length of the fixed-structure kernels, 0: general kernels
+    int p2;   // length of the fixed-structure engine, 0: general kernels
+    bool blu;  // the engine runs Bluestein's convolution (p2 is its length)
   };
   std::vector<Group> groups;
   std::vector<FftGroup> rgroups, cgroups;
@@ -801,12 +830,14 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
   std::stable_sort(rord.begin(), rord.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return std::tie(px.row_p2, px.row_threads, px.row_ept) < std::tie(py.row_p2, py.row_threads, py.row_ept);
+    return std::tie(px.row_blu, px.row_p2, px.row_threads, px.row_ept) <
+           std::tie(py.row_blu, py.row_p2, py.row_threads, py.row_ept);
   });
   std::stable_sort(cord.begin(), cord.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return std::tie(px.col_p2, px.col_threads, px.col_ept) < std::tie(py.col_p2, py.col_threads, py.col_ept);
+    return std::tie(px.col_blu, px.col_p2, px.col_threads, px.col_ept) <
+           std::tie(py.col_blu, py.col_p2, py.col_threads, py.col_ept);
   });
   std::vector<RowFwdArgs<T>> rf(active.size());
   std::vector<ColArgs<T>> ca(active.size());
@@ -821,8 +852,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
     if (ls.rgroups.empty() || ls.rgroups.back().threads != p.row_threads || ls.rgroups.back().ept != p.row_ept ||
-        ls.rgroups.back().p2 != p.row_p2)
-      ls.rgroups.push_back({p.row_ept, p.row_threads, (int)q, 0, 0, 0, p.row_p2});
+        ls.rgroups.back().p2 != p.row_p2 || ls.rgroups.back().blu != p.row_blu)
+      ls.rgroups.push_back({p.row_ept, p.row_threads, (int)q, 0, 0, 0, p.row_p2, p.row_blu});
     LaunchSet::FftGroup& g = ls.rgroups.back();
     RowFwdArgs<T>& f = rf[q];
     std::memset(&f, 0, sizeof(f));
@@ -855,8 +886,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
     if (ls.cgroups.empty() || ls.cgroups.back().threads != p.col_threads || ls.cgroups.back().ept != p.col_ept ||
-        ls.cgroups.back().p2 != p.col_p2)
-      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0, p.col_p2});
+        ls.cgroups.back().p2 != p.col_p2 || ls.cgroups.back().blu != p.col_blu)
+      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0, p.col_p2, p.col_blu});
     LaunchSet::FftGroup& g = ls.cgroups.back();
     ColArgs<T>& k = ca[q];
     std::memset(&k, 0, sizeof(k));
@@ -909,9 +940,10 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t1(1, st);
     const RowFwdArgs<T>* tab = wsp<RowFwdArgs<T>>(ws, b.off_tab[fwd_tab]);
     for (const auto& g : ls.rgroups)
-      if ((e = g.p2 ? launch_rows_fwd_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
-                    : launch_rows_fwd(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
-                                      st)) != hipSuccess)
+      if ((e = g.blu  ? launch_rows_fwd_blu(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+               : g.p2 ? launch_rows_fwd_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                      : launch_rows_fwd(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
+                                        st)) != hipSuccess)
         return e;
     t1.stop();
     if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -920,8 +952,9 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t2(2, st);
     const ColArgs<T>* tab = wsp<ColArgs<T>>(ws, b.off_tab[3]);
     for (const auto& g : ls.cgroups)
-      if ((e = g.p2 ? launch_cols_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
-                    : launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
+      if ((e = g.blu  ? launch_cols_blu(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+               : g.p2 ? launch_cols_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                      : launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
           hipSuccess)
         return e;
     t2.stop();
@@ -931,9 +964,10 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t3(3, st);
     const RowInvArgs<T>* tab = wsp<RowInvArgs<T>>(ws, b.off_tab[inv_tab]);
     for (const auto& g : ls.rgroups)
-      if ((e = g.p2 ? launch_rows_inv_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
-                    : launch_rows_inv(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
-                                      st)) != hipSuccess)
+      if ((e = g.blu  ? launch_rows_inv_blu(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+               : g.p2 ? launch_rows_inv_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+                      : launch_rows_inv(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds,
+                                        st)) != hipSuccess)
         return e;
     t3.stop();
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
@@ -1186,7 +1220,8 @@ std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, 
   for (size_t i = 0; i < b.im.size(); ++i) {
     const Plan& p = b.im[i].plan;
     const int pi[] = {p.g.ntr,          p.g.ntc,       p.kpw,            p.pf ? 1 : 0, p.row_p2,
-                      p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads, p.col_p2};
+                      p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads, p.col_p2,
+                      p.row_blu ? 1 : 0, p.col_blu ? 1 : 0};
     key_add(k, pi, sizeof(pi));
   }
   return k;
@@ -1601,8 +1636,7 @@ void tuning_of(const Plan& p, segsalsa_tuning& t) {
   t.tile_cols = p.g.TC;
   t.classes_per_wave = p.kpw;
   t.prefetch = p.pf ? 1 : 0;
-  t.generic_fft = (p.row_p2 == 0 && p2_length(p.W) && !p.frow.blu) || (p.col_p2 == 0 && p2_length(p.H) && !p.fcol.blu)
-                      ? 1 : 0;
+  t.generic_fft = (p.row_p2 == 0 && engine_length(p.W)) || (p.col_p2 == 0 && engine_length(p.H)) ? 1 : 0;
   t.rows_per_block = p.rows_per_block;
   t.row_threads = p.row_threads;
   t.cols_per_block = p.cols_per_block;
@@ -1774,8 +1808,8 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
       return SEGSALSA_OK;
     };
     segsalsa_status s2 = SEGSALSA_OK;
-    const bool pow2 = p2_length(W) && !p.frow.blu;
-    if (pow2) {   // the fixed-structure kernels: rows per workgroup (threads follow)
+    const bool pow2 = engine_length(W);
+    if (pow2) {   // the fixed-structure engine: rows per workgroup (threads follow)
       for (int rpb : {1, 2, 4, 8, 16}) {
         if (rpb > H) break;
         segsalsa_tuning cand = cur;
@@ -1992,6 +2026,22 @@ segsalsa_status segsalsa_str_batch_workspace_size(int32_t n_images, const segsal
   segsalsa_status s = batch_common(n_images, images, params, precision, b);
   if (s != SEGSALSA_OK) return s;
   *bytes = b.total;
+  return SEGSALSA_OK;
+}
+
+segsalsa_status segsalsa_str_batch_plans(int32_t n_images, const segsalsa_image* images,
+                                         const segsalsa_batch_params* params, segsalsa_precision precision,
+                                         segsalsa_tuning* plans) {
+  g_last_error.clear();
+  if (!plans) return fail(SEGSALSA_ERR_INVALID_ARG, "plans is NULL");
+  Batch b;
+  segsalsa_status s = batch_common(n_images, images, params, precision, b);
+  if (s != SEGSALSA_OK) return s;
+  for (int i = 0; i < n_images; ++i) {
+    segsalsa_tuning t{};
+    tuning_of(b.im[i].plan, t);
+    plans[i] = t;
+  }
   return SEGSALSA_OK;
 }
 

@@ -225,11 +225,6 @@ __device__ __forceinline__ void stage_generic(lptr<C2<T>> buf, int N, int R, int
   __syncthreads();
 }
 
-template <typename T>
-__device__ inline C2<T> cmul(C2<T> a, C2<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-
 
 // Mixed-radix Stockham DFT over the given factors (unnormalised).
 template <typename T, int EPT, typename TW>

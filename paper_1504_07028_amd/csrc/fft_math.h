@@ -32,6 +32,8 @@ template <typename T>
 __device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename T>
 __device__ inline C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ inline C2<T> cmul(C2<T> a, C2<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 // multiply by +i (sg = +1) or -i (sg = -1)
 template <typename T>
 __device__ inline C2<T> cmuli(C2<T> a, T sg) { return {-sg * a.y, sg * a.x}; }

@@ -81,6 +81,19 @@ hipError_t launch_rows_inv_p2(const RowInvArgs<float>* d, int n, int blocks, int
                               hipStream_t st);
 hipError_t launch_rows_inv_p2(const RowInvArgs<double>* d, int n, int blocks, int N, int threads, size_t lds,
                               hipStream_t st);
+// FFT passes for sides that take Bluestein's transform, with the two
+// length-MM convolution FFTs (MM in 64 .. 4096) on the same engine
+// (fft_blu_kernels.hip): threads = (rows or columns per block) * MM / 16.
+hipError_t launch_rows_fwd_blu(const RowFwdArgs<float>* d, int n, int blocks, int MM, int threads, size_t lds,
+                               hipStream_t st);
+hipError_t launch_rows_fwd_blu(const RowFwdArgs<double>* d, int n, int blocks, int MM, int threads, size_t lds,
+                               hipStream_t st);
+hipError_t launch_cols_blu(const ColArgs<float>* d, int n, int blocks, int MM, int threads, size_t lds, hipStream_t st);
+hipError_t launch_cols_blu(const ColArgs<double>* d, int n, int blocks, int MM, int threads, size_t lds, hipStream_t st);
+hipError_t launch_rows_inv_blu(const RowInvArgs<float>* d, int n, int blocks, int MM, int threads, size_t lds,
+                               hipStream_t st);
+hipError_t launch_rows_inv_blu(const RowInvArgs<double>* d, int n, int blocks, int MM, int threads, size_t lds,
+                               hipStream_t st);
 constexpr int kP2Min = 64, kP2Max = 4096;
 inline bool p2_length(int n) { return n >= kP2Min && n <= kP2Max && (n & (n - 1)) == 0; }
 // LDS elements per transform of the power-of-two kernels (one pad element every 16, plus one)
@@ -183,6 +196,15 @@ __host__ __device__ constexpr int adj_max_threads() {
   constexpr int wps = 512 / vg;
   constexpr int w = wps >= 4 ? 4 : (wps < 1 ? 1 : wps);
   return w * 4 * 64;
+}
+
+// Waves per SIMD the adjoint kernel is compiled for: FP32 with one class per
+// wavefront and M <= 1 fits 128 VGPRs (two 8-wave workgroups per compute
+// unit, so one runs its FP64 closed forms while the other streams); the
+// others keep the register budget of a single workgroup.
+template <typename T, int M, int KPW>
+__host__ __device__ constexpr int adj_min_waves() {
+  return sizeof(T) == 4 && M <= 1 && KPW == 1 ? 4 : 1;
 }
 
 inline int adj_max_threads_rt(bool fp64, int M, int kpw) {

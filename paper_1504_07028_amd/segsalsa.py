@@ -102,6 +102,9 @@ def lib():
     L.segsalsa_str_batch_workspace_size.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params),
                                                     c_int32, POINTER(c_size_t)]
     L.segsalsa_str_batch_workspace_size.restype = c_int32
+    L.segsalsa_str_batch_plans.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params), c_int32,
+                                           POINTER(segsalsa_tuning)]
+    L.segsalsa_str_batch_plans.restype = c_int32
     L.segsalsa_str_solve_batch.argtypes = [c_int32, POINTER(segsalsa_image), POINTER(segsalsa_batch_params), c_int32,
                                            c_void_p, c_void_p, c_void_p, c_size_t, POINTER(segsalsa_stats), c_void_p]
     L.segsalsa_str_solve_batch.restype = c_int32
@@ -304,6 +307,14 @@ def segsalsa_str_batch_workspace_size(images, params: BatchParams, precision: in
     _check(lib().segsalsa_str_batch_workspace_size(len(images), images, ctypes.byref(s), int(precision),
                                                    ctypes.byref(n)))
     return int(n.value)
+
+
+def segsalsa_str_batch_plans(images, params: BatchParams, precision: int):
+    """The launch shapes each image of the batch runs with (dicts of TUNING_FIELDS)."""
+    s = params.c_struct()
+    out = (segsalsa_tuning * len(images))()
+    _check(lib().segsalsa_str_batch_plans(len(images), images, ctypes.byref(s), int(precision), out))
+    return [_tuning_dict(t) for t in out]
 
 
 def segsalsa_str_solve_batch(images, params: BatchParams, inp, z_out, workspace, stats: bool = False, stream=None):

@@ -365,3 +365,21 @@ def test_prefetch_entries_only_where_built(clean_table):
         with pytest.raises(S.SegsalsaError) as e:
             S.segsalsa_tuning_set(16, 40, 60, M, prec, dict(classes_per_wave=2, prefetch=1))
         assert e.value.status == UNSUPPORTED
+
+
+def test_batch_plans_depend_on_transform_length_only(S):
+    """In a batch of several images the FFT blocking is a function of the transform length, so images
+    of one length share a launch: equal column lengths (211 and 227 both take Bluestein over 512
+    points; 96 and 300 take the general kernels) and equal row kinds get equal thread counts."""
+    shapes = [(4, 211, 300), (8, 227, 301), (9, 96, 227), (16, 300, 96)]   # (K, H, W)
+    imgs, _ = S.image_table(shapes, [1.0] * 4, [1.0] * 4)
+    params = S.BatchParams(1, [1.0 / 3] * 9, 1.0, 10)
+    plans = S.segsalsa_str_batch_plans(imgs, params, 0)
+    assert len(plans) == 4 and all(p["tile_rows"] > 0 and p["tile_cols"] > 0 for p in plans)
+    assert plans[0]["col_threads"] == plans[1]["col_threads"] == 16 * 32      # 16 columns of 512 / 16 threads
+    assert plans[2]["col_threads"] == plans[3]["col_threads"] == 512         # general kernels: 4096 elements / 8
+    assert plans[0]["row_threads"] == plans[1]["row_threads"] == 256          # general rows: 2048 elements / 8
+    assert plans[2]["row_threads"] == 8 * 32                                  # 227 -> Bluestein over 512
+    # a single image of one of these shapes is planned on its own work instead
+    single, _ = S.segsalsa_tuning_get(4, 211, 300, 1, 0)
+    assert single["tile_rows"] == plans[0]["tile_rows"] and single["tile_cols"] == plans[0]["tile_cols"]

@@ -32,6 +32,12 @@ SMALL_CASES = [
     (97, 509, 3, 1, 1.0, 4),     # a direct 97-point stage; Bluestein (M = 1024) for 509
     (122, 86, 5, 2, math.inf, 4),  # 2 x 61 and 2 x 43
     (211, 101, 2, 1, 1.0, 3),    # primes just above the direct-stage limit: Bluestein both ways
+    # Bluestein on the fixed-structure engine: convolution lengths 256 .. 4096, an odd K (a lone class
+    # in the last pair), ragged last row and column blocks
+    (113, 227, 5, 1, 1.0, 4),    # M = 256 columns, 512 rows
+    (1031, 6, 3, 1, 2.0, 3),     # M = 4096 columns (one column of 256 threads per workgroup)
+    (7, 1031, 4, 2, 1.0, 3),     # M = 4096 rows
+    (606, 37, 3, 0, math.inf, 3),  # 606 = 2 x 3 x 101: M = 2048 columns
     # power-of-two sides (the fixed-structure kernels, 64 .. 4096), alone or next to a general side
     (64, 128, 5, 1, 1.0, 5),
     (128, 64, 16, 2, math.inf, 4),

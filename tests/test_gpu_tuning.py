@@ -31,7 +31,11 @@ CASES = [
                         cols_per_block=16, col_threads=128)),
     (53, 47, 9, 2, dict(tile_rows=4, tile_cols=8, classes_per_wave=4, rows_per_block=1, row_threads=1024,
                         cols_per_block=1, col_threads=64)),
-    (101, 40, 5, 1, dict(rows_per_block=2, row_threads=192, cols_per_block=8, col_threads=512)),   # Bluestein columns
+    # Bluestein columns in the general kernels (in LDS) and on the fixed-structure engine (M = 256:
+    # 16 threads per column)
+    (101, 40, 5, 1, dict(generic_fft=1, rows_per_block=2, row_threads=192, cols_per_block=8, col_threads=512)),
+    (101, 40, 5, 1, dict(rows_per_block=2, row_threads=192, cols_per_block=12, col_threads=192)),
+    (43, 131, 3, 1, dict(rows_per_block=6, row_threads=192, cols_per_block=5, col_threads=320)),   # M = 512 rows
 ]
 
 
