@@ -323,6 +323,10 @@ typedef struct {
                                     Bluestein with a convolution length M of 64 .. 4096 (M / 16 threads
                                     per transform); with the engine, threads are rows or columns per
                                     block times N / 16 or M / 16                                       */
+  int32_t col_dft;               /* 1: the column pass by DFTs (column DFT, symbol, inverse DFT); 0: by
+                                    the exact periodic tridiagonal recursions per column frequency,
+                                    cols_per_block columns of ceil(H / 32) (FP64: ceil(H / 16)) threads
+                                    each, col_threads >= their product                                 */
   int32_t rows_per_block;        /* rows per workgroup of the row DFT passes (> 0), or 0               */
   int32_t row_threads;           /* threads per row workgroup, a multiple of 64 in [64, 1024], or 0    */
   int32_t cols_per_block;        /* columns per workgroup of the column pass (> 0), or 0               */

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsegsalsa.so")
-SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "fft_pow2_kernels.hip", "fft_blu_kernels.hip",
+SOURCES = ["api.hip", "prox_kernel.hip", "fft_kernels.hip", "fft_pow2_kernels.hip", "fft_blu_kernels.hip", "tri_kernels.hip",
            "misc_kernels.hip",
            "residual_kernels.hip", "adjoint_kernels.hip"]
 ARCH = "gfx950"

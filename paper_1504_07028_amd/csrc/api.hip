@@ -99,6 +99,8 @@ FftPlanDev make_fft_plan(int N) {
   return p;
 }
 
+constexpr int kTriThreads = 512;   // workgroup size of the tridiagonal column pass (see plan_with)
+
 // Lengths the fixed-structure engine runs: powers of two 64 .. 4096, and
 // lengths taking Bluestein whose convolution length is in that range.
 bool engine_length(int n) {
@@ -122,6 +124,7 @@ struct Plan {
   int rows_per_block, row_threads, row_ept;
   int row_p2, col_p2;   // length of the fixed-structure row (column) engine, 0: general kernels
   bool row_blu, col_blu;   // the engine runs the Bluestein convolution (its length is frow.M / fcol.M)
+  bool col_tri;            // the column pass by the tridiagonal recursions (col_ept rows per thread)
   size_t row_lds;
   int cols_per_block, col_threads, col_ept;
   size_t col_lds;
@@ -485,7 +488,38 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     p.row_ept = ept;
     p.row_lds = lds_of(rpb);
   }
-  if (p.col_p2) {
+  p.col_tri = !tn.col_dft;
+  if (p.col_tri) {
+    // The tridiagonal recursions: lpt rows per thread, ceil(H / lpt) threads
+    // per column; about 512 threads of adjacent columns per workgroup (fewer
+    // for a single image too small to fill the GPU with them); in a batch,
+    // 512 threads for every column length.
+    const int lpt = p.fp64 ? 16 : 32;
+    const int tpc = ceil_div(H, lpt);
+    long long cb;
+    if (tn.cols_per_block > 0) {
+      cb = std::min<long long>(tn.cols_per_block, W);
+    } else {
+      cb = std::max(1, kTriThreads / tpc);
+      if (!batch) {
+        cb = std::min<long long>(cb, W);
+        while (cb > 1 && (long long)p.P * ceil_div(W, (int)cb) < 2 * kTargetGroups) cb = (cb + 1) / 2;
+      }
+    }
+    const long long need = cb * tpc;
+    long long thr = tn.col_threads > 0 ? tn.col_threads
+                    : batch && tn.cols_per_block <= 0 && need <= kTriThreads ? kTriThreads
+                                                                             : (need + 63) / 64 * 64;
+    if (thr < need || thr > kFftMaxThreads)
+      return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld columns of %d chunks need %lld threads (%lld given, at most %d)", cb,
+                  tpc, need, thr, kFftMaxThreads);
+    p.col_p2 = 0;
+    p.col_blu = false;
+    p.cols_per_block = (int)cb;
+    p.col_threads = (int)thr;
+    p.col_ept = lpt;
+    p.col_lds = tri_lds((int)thr, p.ts);
+  } else if (p.col_p2) {
     const int tpt = p.col_p2 / 16;
     // default: about 512 threads (FP64: 256), at least one wavefront, one workgroup per CU when there are the columns
     long long cb = tn.cols_per_block > 0 ? std::min<long long>(tn.cols_per_block, W)
@@ -745,6 +779,7 @@ struct LaunchSet {
     size_t lds;
     int p2;   // length of the fixed-structure engine, 0: general kernels
     bool blu;  // the engine runs Bluestein's convolution (p2 is its length)
+    bool tri;  // columns: the tridiagonal recursions (ept rows per thread)
   };
   std::vector<Group> groups;
   std::vector<FftGroup> rgroups, cgroups;
@@ -836,8 +871,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
   std::stable_sort(cord.begin(), cord.end(), [&](int x, int y) {
     const Plan& px = b.im[x].plan;
     const Plan& py = b.im[y].plan;
-    return std::tie(px.col_blu, px.col_p2, px.col_threads, px.col_ept) <
-           std::tie(py.col_blu, py.col_p2, py.col_threads, py.col_ept);
+    return std::tie(px.col_tri, px.col_blu, px.col_p2, px.col_threads, px.col_ept) <
+           std::tie(py.col_tri, py.col_blu, py.col_p2, py.col_threads, py.col_ept);
   });
   std::vector<RowFwdArgs<T>> rf(active.size());
   std::vector<ColArgs<T>> ca(active.size());
@@ -886,8 +921,8 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     const Plan& p = r.plan;
     void* base = wsp<char>(ws, r.base);
     if (ls.cgroups.empty() || ls.cgroups.back().threads != p.col_threads || ls.cgroups.back().ept != p.col_ept ||
-        ls.cgroups.back().p2 != p.col_p2 || ls.cgroups.back().blu != p.col_blu)
-      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0, p.col_p2, p.col_blu});
+        ls.cgroups.back().p2 != p.col_p2 || ls.cgroups.back().blu != p.col_blu || ls.cgroups.back().tri != p.col_tri)
+      ls.cgroups.push_back({p.col_ept, p.col_threads, (int)q, 0, 0, 0, p.col_p2, p.col_blu, p.col_tri});
     LaunchSet::FftGroup& g = ls.cgroups.back();
     ColArgs<T>& k = ca[q];
     std::memset(&k, 0, sizeof(k));
@@ -952,7 +987,8 @@ hipError_t enqueue_fft(const Batch& b, const LaunchSet& ls, void* ws, hipStream_
     PhaseTimer t2(2, st);
     const ColArgs<T>* tab = wsp<ColArgs<T>>(ws, b.off_tab[3]);
     for (const auto& g : ls.cgroups)
-      if ((e = g.blu  ? launch_cols_blu(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
+      if ((e = g.tri  ? launch_cols_tri(tab + g.first, g.count, g.blocks, g.ept, g.threads, g.lds, st)
+               : g.blu  ? launch_cols_blu(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
                : g.p2 ? launch_cols_p2(tab + g.first, g.count, g.blocks, g.p2, g.threads, g.lds, st)
                       : launch_cols(tab + g.first, g.count, g.blocks, g.ept, g.threads, narrow(g.threads), g.lds, st)) !=
           hipSuccess)
@@ -1221,7 +1257,7 @@ std::vector<unsigned char> graph_key(const Batch& b, void* ws, void* const* zs, 
     const Plan& p = b.im[i].plan;
     const int pi[] = {p.g.ntr,          p.g.ntc,       p.kpw,            p.pf ? 1 : 0, p.row_p2,
                       p.rows_per_block, p.row_threads, p.cols_per_block, p.col_threads, p.col_p2,
-                      p.row_blu ? 1 : 0, p.col_blu ? 1 : 0};
+                      p.row_blu ? 1 : 0, p.col_blu ? 1 : 0, p.col_tri ? 1 : 0};
     key_add(k, pi, sizeof(pi));
   }
   return k;
@@ -1636,7 +1672,8 @@ void tuning_of(const Plan& p, segsalsa_tuning& t) {
   t.tile_cols = p.g.TC;
   t.classes_per_wave = p.kpw;
   t.prefetch = p.pf ? 1 : 0;
-  t.generic_fft = (p.row_p2 == 0 && engine_length(p.W)) || (p.col_p2 == 0 && engine_length(p.H)) ? 1 : 0;
+  t.col_dft = p.col_tri ? 0 : 1;
+  t.generic_fft = (p.row_p2 == 0 && engine_length(p.W)) || (!p.col_tri && p.col_p2 == 0 && engine_length(p.H)) ? 1 : 0;
   t.rows_per_block = p.rows_per_block;
   t.row_threads = p.row_threads;
   t.cols_per_block = p.cols_per_block;
@@ -1652,6 +1689,7 @@ segsalsa_status check_tuning_fields(const segsalsa_tuning& t) {
   if (t.prefetch != 0 && t.prefetch != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "prefetch = %d (0 or 1)", t.prefetch);
   if (t.generic_fft != 0 && t.generic_fft != 1)
     return fail(SEGSALSA_ERR_INVALID_ARG, "generic_fft = %d (0 or 1)", t.generic_fft);
+  if (t.col_dft != 0 && t.col_dft != 1) return fail(SEGSALSA_ERR_INVALID_ARG, "col_dft = %d (0 or 1)", t.col_dft);
   if (t.rows_per_block < 0 || t.cols_per_block < 0)
     return fail(SEGSALSA_ERR_INVALID_ARG, "rows/cols per block must be >= 0");
   if (!thr_ok(t.row_threads) || !thr_ok(t.col_threads))
@@ -1834,16 +1872,16 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
     cur = win;
     cur_cols = 1e30;   // re-measured below with the chosen row kernels
   }
-  // 3. column blocking, by the column pass
+  // 3. column pass (the tridiagonal recursions or the DFTs) and its
+  // blocking, by the time of the column pass
   {
-    Plan p;
-    if (plan_with(K, H, W, c, cur, p) != SEGSALSA_OK) return fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
-    const int Lc = p.fcol.blu ? p.fcol.M : H;
     if (!measure(cur, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
     segsalsa_tuning win = cur;
     double win_t = t[3];
     auto consider = [&](const segsalsa_tuning& cand) -> segsalsa_status {
-      if (cand.cols_per_block == cur.cols_per_block && cand.col_threads == cur.col_threads) return SEGSALSA_OK;
+      if (cand.cols_per_block == cur.cols_per_block && cand.col_threads == cur.col_threads &&
+          cand.col_dft == cur.col_dft)
+        return SEGSALSA_OK;
       if (!measure(cand, t, err)) return err;
       if (t[3] < win_t) {
         win = cand;
@@ -1852,24 +1890,40 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
       return SEGSALSA_OK;
     };
     segsalsa_status s3 = SEGSALSA_OK;
-    if (p.col_p2) {   // the fixed-structure kernels: columns per workgroup (threads follow)
-      for (int cb : {1, 2, 4, 8, 16}) {
-        if (cb > W) break;
-        segsalsa_tuning cand = cur;
-        cand.cols_per_block = cb;
-        cand.col_threads = 0;
-        if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
-      }
-    } else {
-      for (int cb : {1, 2, 4, 8, 16, 32}) {
-        if (cb > W) break;
-        for (int per : {2, 4, 8, 16}) {
-          segsalsa_tuning cand = cur;
+    for (int cb : {1, 2, 4, 8, 16, 32, 64}) {   // the recursions: columns per workgroup (threads follow)
+      if (cb > W) break;
+      segsalsa_tuning cand = cur;
+      cand.col_dft = 0;
+      cand.cols_per_block = cb;
+      cand.col_threads = 0;
+      if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
+    }
+    segsalsa_tuning dft = cur;
+    dft.col_dft = 1;
+    dft.cols_per_block = dft.col_threads = 0;
+    Plan p;
+    if (plan_with(K, H, W, c, dft, p) == SEGSALSA_OK) {
+      const int Lc = p.fcol.blu ? p.fcol.M : H;
+      if (p.col_p2) {   // the fixed-structure engine: columns per workgroup (threads follow)
+        for (int cb : {1, 2, 4, 8, 16}) {
+          if (cb > W) break;
+          segsalsa_tuning cand = dft;
           cand.cols_per_block = cb;
-          cand.col_threads = fft_threads_for((long long)cb * Lc, per);
           if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
         }
+      } else {
+        for (int cb : {1, 2, 4, 8, 16, 32}) {
+          if (cb > W) break;
+          for (int per : {2, 4, 8, 16}) {
+            segsalsa_tuning cand = dft;
+            cand.cols_per_block = cb;
+            cand.col_threads = fft_threads_for((long long)cb * Lc, per);
+            if ((s3 = consider(cand)) != SEGSALSA_OK) return s3;
+          }
+        }
       }
+    } else {
+      g_last_error = saved;
     }
     cur = win;
   }
@@ -1878,7 +1932,11 @@ segsalsa_status autotune_t(const segsalsa_problem* pr, const Common& c, const vo
   double tuned_round = t[0];
   if (!measure(base, t, err)) return err != SEGSALSA_OK ? err : fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
   const double base_again = std::min(base_round, t[0]);
-  best = tuned_round <= base_again ? cur : base;
+  // the winner with every field filled in (threads that follow from the blocking included)
+  Plan pw;
+  if (plan_with(K, H, W, c, tuned_round <= base_again ? cur : base, pw) != SEGSALSA_OK)
+    return fail(SEGSALSA_ERR_DEVICE, "autotune: lost the plan");
+  tuning_of(pw, best);
   best.us_per_round = 1e3 * std::min(tuned_round, base_again);
   g_last_error = saved;
   return SEGSALSA_OK;
@@ -2275,11 +2333,11 @@ segsalsa_status segsalsa_tuning_save(const char* path) {
       std::snprintf(buf, sizeof(buf),
                     "%s\n    {\"K\": %d, \"H\": %d, \"W\": %d, \"M\": %d, \"precision\": \"%s\", \"tile_rows\": %d, "
                     "\"tile_cols\": %d, \"classes_per_wave\": %d, \"prefetch\": %d, \"generic_fft\": %d, "
-                    "\"rows_per_block\": %d, \"row_threads\": %d, \"cols_per_block\": %d, \"col_threads\": %d, "
-                    "\"us_per_round\": %.3f}",
+                    "\"col_dft\": %d, \"rows_per_block\": %d, \"row_threads\": %d, \"cols_per_block\": %d, "
+                    "\"col_threads\": %d, \"us_per_round\": %.3f}",
                     first ? "" : ",", k.K, k.H, k.W, k.M, k.fp64 ? "fp64" : "fp32", t.tile_rows, t.tile_cols,
-                    t.classes_per_wave, t.prefetch, t.generic_fft, t.rows_per_block, t.row_threads, t.cols_per_block,
-                    t.col_threads, t.us_per_round);
+                    t.classes_per_wave, t.prefetch, t.generic_fft, t.col_dft, t.rows_per_block, t.row_threads,
+                    t.cols_per_block, t.col_threads, t.us_per_round);
       txt += buf;
       first = false;
     }
@@ -2315,7 +2373,7 @@ segsalsa_status segsalsa_tuning_load(const char* path, int32_t* loaded, int32_t*
     if (end == std::string::npos) break;
     const std::string obj = txt.substr(pos, end - pos + 1);
     pos = end + 1;
-    double K, H, W, M, tr, tc, kpw, rpb, rt, cpb, ct, us = 0.0, pf = 0.0, gf = 0.0;
+    double K, H, W, M, tr, tc, kpw, rpb, rt, cpb, ct, us = 0.0, pf = 0.0, gf = 0.0, cd = 0.0;
     std::string prec;
     if (!(json_number(obj, "K", K) && json_number(obj, "H", H) && json_number(obj, "W", W) &&
           json_number(obj, "M", M) && json_string(obj, "precision", prec) && json_number(obj, "tile_rows", tr) &&
@@ -2329,9 +2387,11 @@ segsalsa_status segsalsa_tuning_load(const char* path, int32_t* loaded, int32_t*
     (void)json_number(obj, "us_per_round", us);
     (void)json_number(obj, "prefetch", pf);
     (void)json_number(obj, "generic_fft", gf);
+    (void)json_number(obj, "col_dft", cd);
     segsalsa_tuning t{};
     t.tile_rows = (int)tr; t.tile_cols = (int)tc; t.classes_per_wave = (int)kpw; t.prefetch = (int)pf;
     t.generic_fft = (int)gf;
+    t.col_dft = (int)cd;
     t.rows_per_block = (int)rpb; t.row_threads = (int)rt; t.cols_per_block = (int)cpb; t.col_threads = (int)ct;
     t.us_per_round = us;
     if (segsalsa_tuning_set((int)K, (int)H, (int)W, (int)M, prec == "fp64" ? SEGSALSA_FP64 : SEGSALSA_FP32, &t) ==

@@ -94,6 +94,14 @@ hipError_t launch_rows_inv_blu(const RowInvArgs<float>* d, int n, int blocks, in
                                hipStream_t st);
 hipError_t launch_rows_inv_blu(const RowInvArgs<double>* d, int n, int blocks, int MM, int threads, size_t lds,
                                hipStream_t st);
+// Column pass by the periodic tridiagonal recursions (tri_kernels.hip): lpt
+// rows per thread (16 or 32), at least cols_per_block * ceil(H / lpt) threads,
+// tri_lds(threads, element size) bytes of LDS.
+hipError_t launch_cols_tri(const ColArgs<float>* d, int n, int blocks, int lpt, int threads, size_t lds,
+                           hipStream_t st);
+hipError_t launch_cols_tri(const ColArgs<double>* d, int n, int blocks, int lpt, int threads, size_t lds,
+                           hipStream_t st);
+inline size_t tri_lds(int threads, size_t ts) { return ((2 * (size_t)threads * ts + 15) & ~size_t(15)) + 4 * (size_t)threads * ts; }
 constexpr int kP2Min = 64, kP2Max = 4096;
 inline bool p2_length(int n) { return n >= kP2Min && n <= kP2Max && (n & (n - 1)) == 0; }
 // LDS elements per transform of the power-of-two kernels (one pad element every 16, plus one)

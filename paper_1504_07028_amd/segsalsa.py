@@ -55,11 +55,11 @@ class segsalsa_batch_params(ctypes.Structure):
 
 class segsalsa_tuning(ctypes.Structure):
     _fields_ = [("tile_rows", c_int32), ("tile_cols", c_int32), ("classes_per_wave", c_int32), ("prefetch", c_int32),
-                ("generic_fft", c_int32), ("rows_per_block", c_int32), ("row_threads", c_int32),
+                ("generic_fft", c_int32), ("col_dft", c_int32), ("rows_per_block", c_int32), ("row_threads", c_int32),
                 ("cols_per_block", c_int32), ("col_threads", c_int32), ("us_per_round", c_double)]
 
 
-TUNING_FIELDS = ("tile_rows", "tile_cols", "classes_per_wave", "prefetch", "generic_fft", "rows_per_block",
+TUNING_FIELDS = ("tile_rows", "tile_cols", "classes_per_wave", "prefetch", "generic_fft", "col_dft", "rows_per_block",
                  "row_threads", "cols_per_block", "col_threads", "us_per_round")
 # Launch shapes measured by segsalsa_str_autotune on an MI355X for the shapes
 # the benchmark and the tests run (written by `python -m paper_1504_07028_amd.autotune`).

@@ -261,8 +261,8 @@ def test_tuning_set_get_and_workspace(clean_table):
     assert not tuned and plan["tile_rows"] > 0 and plan["row_threads"] % 64 == 0
     st, before = status_of_size(S, base_problem(S, K=K, H=H, W=W))
     assert st == OK
-    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, prefetch=1, generic_fft=0, rows_per_block=3, row_threads=128, cols_per_block=4,
-                col_threads=192, us_per_round=12.5)
+    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, prefetch=1, generic_fft=0, col_dft=0, rows_per_block=3,
+                row_threads=128, cols_per_block=4, col_threads=192, us_per_round=12.5)
     S.segsalsa_tuning_set(K, H, W, M, 0, want)
     got, tuned = S.segsalsa_tuning_get(K, H, W, M, 0)
     assert tuned and got == want
@@ -283,6 +283,9 @@ def test_tuning_set_get_and_workspace(clean_table):
     (dict(rows_per_block=40, row_threads=64), UNSUPPORTED),               # 40 x 60 elements > 16 per thread
     (dict(prefetch=2), INVALID),
     (dict(prefetch=1, classes_per_wave=1), UNSUPPORTED),                  # prefetching build: 2 classes per wave
+    (dict(col_dft=2), INVALID),
+    (dict(cols_per_block=64, col_threads=64), UNSUPPORTED),               # 64 columns x 2 chunks of 32 rows
+    (dict(col_dft=1, cols_per_block=32, col_threads=64), UNSUPPORTED),    # the DFT pass: 32 x 40 elements > 16 each
 ])
 def test_tuning_rejects_entries_that_do_not_fit(clean_table, bad, code):
     S = clean_table
@@ -338,7 +341,7 @@ def test_shipped_cache_is_read(S):
         assert tuned
         # fields the entry leaves at 0 (threads of the power-of-two FFT kernels) are filled in by the planner
         for f in S.TUNING_FIELDS[:-1]:
-            assert e[f] == 0 or got[f] == e[f], (e, f, got[f])
+            assert e.get(f, 0) == 0 or got[f] == e[f], (e, f, got[f])
 
 
 def test_autotune_argument_errors(S):

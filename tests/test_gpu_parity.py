@@ -62,6 +62,41 @@ def test_small_grids(H, W, K, M, p, iters, dtype):
     check_err(err, dtype)
 
 
+# the column pass by DFTs (the planner's default is the tridiagonal recursions): general mixed-radix
+# and direct prime stages, Bluestein in LDS and on the fixed-structure engine, power-of-two lengths
+DFT_COLUMN_CASES = [
+    (47, 53, 4, 1, 1.0, 5, 0),
+    (122, 86, 5, 2, math.inf, 4, 0),
+    (97, 509, 3, 1, 1.0, 4, 0),
+    (211, 101, 2, 1, 1.0, 3, 0),
+    (211, 101, 2, 1, 1.0, 3, 1),     # the general kernels' Bluestein (in LDS)
+    (606, 37, 3, 0, math.inf, 3, 0),
+    (1031, 6, 3, 1, 2.0, 3, 0),
+    (128, 64, 16, 2, math.inf, 4, 0),
+    (1024, 8, 2, 1, 1.0, 3, 0),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("H,W,K,M,p,iters,generic", DFT_COLUMN_CASES)
+def test_small_grids_dft_columns(H, W, K, M, p, iters, generic, dtype):
+    S = need_gpu()
+    prec = S._prec(dtype)
+    S.segsalsa_tuning_set(K, H, W, M, prec, dict(col_dft=1, generic_fft=generic))
+    try:
+        plan, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+        assert tuned and plan["col_dft"] == 1
+        say(f"case DFT columns H={H} W={W} K={K} M={M} p={p} iters={iters} {dtype}: {plan}")
+        probs, _, _, c = problem_inputs(H, W, K, M, seed=H * 131 + W * 7 + K)
+        z, *_ = gpu_solve(S, probs, c, M, p, 0.8, 1.3, iters, dtype)
+    finally:
+        S.segsalsa_tuning_set(K, H, W, M, prec, None)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    check_err(err, dtype)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
 def test_plain_64x64(dtype):
     """The 64x64, K = 4, 3x3 patch, Schatten-1, 100-round workload."""

@@ -31,10 +31,14 @@ CASES = [
                         cols_per_block=16, col_threads=128)),
     (53, 47, 9, 2, dict(tile_rows=4, tile_cols=8, classes_per_wave=4, rows_per_block=1, row_threads=1024,
                         cols_per_block=1, col_threads=64)),
-    # Bluestein columns in the general kernels (in LDS) and on the fixed-structure engine (M = 256:
+    # Bluestein columns by DFTs in the general kernels (in LDS) and on the fixed-structure engine (M = 256:
     # 16 threads per column)
-    (101, 40, 5, 1, dict(generic_fft=1, rows_per_block=2, row_threads=192, cols_per_block=8, col_threads=512)),
-    (101, 40, 5, 1, dict(rows_per_block=2, row_threads=192, cols_per_block=12, col_threads=192)),
+    (101, 40, 5, 1, dict(generic_fft=1, col_dft=1, rows_per_block=2, row_threads=192, cols_per_block=8,
+                         col_threads=512)),
+    (101, 40, 5, 1, dict(col_dft=1, rows_per_block=2, row_threads=192, cols_per_block=12, col_threads=192)),
+    # the tridiagonal column pass with more threads than chunks, and with one column per workgroup
+    (150, 33, 4, 1, dict(cols_per_block=3, col_threads=320)),
+    (70, 9, 3, 2, dict(cols_per_block=1, col_threads=64)),
     (43, 131, 3, 1, dict(rows_per_block=6, row_threads=192, cols_per_block=5, col_threads=320)),   # M = 512 rows
 ]
 
