@@ -303,6 +303,26 @@ def bench_batch(S, torch, synth, steps, warmup, fp32_only=False, graph=True):
     return res
 
 
+def hbm_copy_rate(torch, nbytes=2 << 30, reps=5):
+    """GB/s (read + write) of a plain device-to-device copy of nbytes (torch's copy kernel): the
+    streaming rate a read-modify-write kernel can expect on this GPU, next to the 8 TB/s peak."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def round_roofline(n_units, L, round_us, b=4):
     """Whole round (prox + the three FFT passes) against HBM: (4L + 15) words per pixel*class,
     the prox kernel's (4L + 9) plus the FFT passes' right-hand side and two spectrum round trips."""
@@ -336,7 +356,8 @@ def main():
                          "package's tuning cache")
     ap.add_argument("--tune-rounds", type=int, default=5)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run one plain 512 MiB device-to-device copy (reference for HBM counters)")
+                    help="first run one plain copy of known size, 512 MiB FP32 read from an evicted source "
+                         "and 256 MiB BF16 written (reference for the HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -354,12 +375,17 @@ def main():
     S.lib()
 
     if args.calibrate_copy:
+        # a plain copy of known size for the HBM counters: 512 MiB of FP32 read and written as
+        # 256 MiB of BF16 (its own kernel, named by the BF16 output type), from a source that 2 GiB
+        # written in between has evicted from the L2s and the 256 MB MALL
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+        flush = torch.empty(512 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        flush.fill_(2.0)
         torch.cuda.synchronize()
-        log("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written")
-        del src, dst
+        dst = src.to(torch.bfloat16)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy (FP32 -> BF16): 536870912 bytes read, 268435456 bytes written")
+        del src, dst, flush
 
     if args.sweep:
         print(json.dumps(bench_sweep(S, torch, synth, args.workload, steps=args.steps)), flush=True)
@@ -427,6 +453,7 @@ def main():
     achieved = bytes_launch / (prox["avg_us"] * 1e-6) / 1e9
     src_hash = kernel_source_hash()
     traffic = load_traffic(wl.name, "f32", src_hash)
+    copy_gbs = hbm_copy_rate(torch)
     value = res["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0
     round_us = res["f32"]["ms_per_step"] * 1e3 / max(1, wl.iters)
     out = {
@@ -448,9 +475,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "prox_rhs", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch_alg": bytes_launch,
-                     "avg_launch_us": prox["avg_us"], "kernel_source_hash": src_hash},
+                     "avg_launch_us": prox["avg_us"], "kernel_source_hash": src_hash,
+                     "frac_of_copy": achieved / copy_gbs},
         "round_roofline": round_roofline(wl.n * wl.K, wl.L, round_us),
         "z_err_fp32_vs_fp64": z_err,
+        "hbm_copy_gbs": copy_gbs,
         "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in res["f32"]["phases"].items()},
     }
     if "f64" in res:
