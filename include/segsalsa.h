@@ -215,11 +215,11 @@ segsalsa_status segsalsa_str_batch_workspace_size(int32_t n_images, const segsal
  *   input_packed   device buffer holding every image's input at its in_offset.
  *   z_packed       device buffer receiving every image's z at its out_offset.
  *   stats          HOST, n_images entries or NULL (required with residuals).
- * The result of each image equals, bit for bit, segsalsa_str_solve on that
- * image alone when the tuning table has no entry for its shape (the batch
- * keeps the planner's tiles; its FFT blocking depends on the transform
- * length only, so that images of one length share a launch, and does not
- * change the arithmetic); with an entry, the single solve agrees to rounding.
+ * The result of each image equals segsalsa_str_solve on that image alone to
+ * rounding, and bit for bit when both run the same kernels: the batch keeps
+ * the planner's tiles and plans its FFT blocking by transform length only (so
+ * that images of one length share a launch), which does not change the
+ * arithmetic; they differ where the tuning table has an entry for the shape.
  */
 segsalsa_status segsalsa_str_solve_batch(int32_t n_images, const segsalsa_image *images,
                                          const segsalsa_batch_params *params, segsalsa_precision precision,

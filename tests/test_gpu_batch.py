@@ -133,7 +133,7 @@ def test_batch_workload_fp32_vs_fp64():
     err = max(float(torch.max(torch.abs(a - b.double())).item()) for a, b in zip(z64, z32))
     say(f"  max |z_fp32 - z_fp64| over the batch = {err:.2e}")
     check_err(err, torch.float32, "max |z_fp32 - z_fp64|")
-    # two images of the batch against their own single solves
+    # two images of the batch against their own single solves (the same kernels: bit for bit)
     for i in (0, len(shapes) - 1):
         zs, _ = run_single(S, probs[i], c, B["M"], 1.0, lams[i], mus[i], B["iters"], torch.float64)
         assert torch.equal(z64[i], zs)

@@ -97,6 +97,68 @@ def test_small_grids_dft_columns(H, W, K, M, p, iters, generic, dtype):
     check_err(err, dtype)
 
 
+def engine_length(n):
+    """The fixed-structure engine's length for a side: n for powers of two 64 .. 4096, the Bluestein
+    length (the power of two >= 2n - 1) for sides with a prime factor above 100, else None."""
+    if 64 <= n <= 4096 and n & (n - 1) == 0:
+        return n
+    m, f, big = n, 2, 1
+    while f * f <= m:
+        while m % f == 0:
+            big, m = max(big, f), m // f
+        f += 1
+    big = max(big, m)
+    if big <= 100:
+        return None
+    L = 1
+    while L < 2 * n - 1:
+        L *= 2
+    return L if 64 <= L <= 4096 else None
+
+
+# the fixed-structure engine, forced by tuned blocking: single images this small take the general
+# kernels by default (the engine's 16 values per thread would leave the GPU mostly idle)
+ENGINE_CASES = [
+    (64, 128, 5, 1, 1.0, 5),
+    (128, 64, 16, 2, math.inf, 4),
+    (256, 512, 3, 1, 2.0, 3),
+    (100, 256, 6, 0, 1.0, 4),
+    (1024, 8, 2, 1, 1.0, 3),
+    (8, 4096, 3, 1, 1.0, 3),
+    (97, 509, 3, 1, 1.0, 4),
+    (211, 101, 2, 1, 1.0, 3),
+    (113, 227, 5, 1, 1.0, 4),
+    (7, 1031, 4, 2, 1.0, 3),
+    (606, 37, 3, 0, math.inf, 3),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("H,W,K,M,p,iters", ENGINE_CASES)
+def test_small_grids_engine_forced(H, W, K, M, p, iters, dtype):
+    S = need_gpu()
+    prec = S._prec(dtype)
+    lr, lc = engine_length(W), engine_length(H)
+    tn = dict(col_dft=1)
+    if lr:
+        tn["rows_per_block"] = max(1, 64 // (lr // 16))
+    if lc:
+        tn["cols_per_block"] = max(1, 64 // (lc // 16))
+    S.segsalsa_tuning_set(K, H, W, M, prec, tn)
+    try:
+        plan, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+        assert tuned and plan["generic_fft"] == 0
+        say(f"case engine H={H} W={W} K={K} M={M} p={p} iters={iters} {dtype}: {plan}")
+        probs, _, _, c = problem_inputs(H, W, K, M, seed=H * 131 + W * 7 + K)
+        z, *_ = gpu_solve(S, probs, c, M, p, 0.8, 1.3, iters, dtype)
+    finally:
+        S.segsalsa_tuning_set(K, H, W, M, prec, None)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, p, 0.8, 1.3, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    check_err(err, dtype)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
 def test_plain_64x64(dtype):
     """The 64x64, K = 4, 3x3 patch, Schatten-1, 100-round workload."""
