@@ -95,40 +95,31 @@ __global__ void __launch_bounds__(p2_max_threads<T>()) fft_rows_fwd_blu_kernel(c
   const int nb = min(rpb, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
   const bool has1 = k1 < a.K;
-  const size_t plane = (size_t)a.g.ER * a.g.EC;
   const gptr<const T> acc = glob(a.acc);
   const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   lptr<C2<T>> lds = (lptr<C2<T>>)smem;
-  // Fold: right-hand side = sum of the grown-tile partial sums covering
-  // (r, c), from the fold lists [kFoldStride][n] (count, entries), into each
-  // row's LDS region.  The workgroup's nb * W elements are at most 8 per
-  // thread (W <= MM / 2); each list's first two entries are read with its
-  // count, so the list and data loads of a thread's elements are in flight
-  // together.
+  // Fold (fold_gather): right-hand side = sum of the grown-tile partial sums
+  // covering (r, c); the workgroup's nb * W elements are at most 8 per thread
+  // (W <= MM / 2), gathered into registers first (their loads in flight
+  // together), then stored to each row's LDS region.
   const FastDiv fW(W);
   const int nel = nb * W;
+  T s0[8], s1[8];
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int idx = threadIdx.x + it * blockDim.x;
+    s0[it] = s1[it] = T(0);
+    if (idx < nel) {
+      const int rr = (int)fW.div(idx), c = idx - rr * W;
+      fold_gather(acc, frow + (row0 + rr), fcol + c, H, W, a.g, a.K, k0, has1, s0[it], s1[it]);
+    }
+  }
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
     const int idx = threadIdx.x + it * blockDim.x;
     if (idx < nel) {
       const int rr = (int)fW.div(idx), c = idx - rr * W;
-      const gptr<const int> rl = frow + (row0 + rr);
-      const gptr<const int> cl = fcol + c;
-      const int nr = rl[0], nc = cl[0];
-      const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[W], c1e = cl[2 * W];
-      T s0 = T(0), s1 = T(0);
-      for (int i = 0; i < nr; ++i) {
-        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[(size_t)(1 + i) * H]);
-        const int tr = ri >> kFoldShift, er = ri & kFoldMask;
-        for (int j = 0; j < nc; ++j) {
-          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[(size_t)(1 + j) * W]);
-          const size_t tile = (size_t)tr * a.g.ntc + (cj >> kFoldShift);
-          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & kFoldMask);
-          s0 += acc[off];
-          if (has1) s1 += acc[off + plane];
-        }
-      }
-      stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0, s1});
+      stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0[it], s1[it]});
     }
   }
   __syncthreads();

@@ -370,37 +370,25 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   const gptr<const T> acc = glob(a.acc);
   const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   // right-hand side = sum of the grown-tile partial sums covering (r, c)
-  const size_t plane = (size_t)a.g.ER * a.g.EC;
+  // (fold_gather).  Each thread holds at most EPT of the nb * W elements
+  // (blockDim.x * EPT >= nb * W, as the LDS FFT needs), gathered into
+  // registers first so that their loads are in flight together.
   const bool has1 = k1 < a.K;
   const FastDiv fW(W);
-  // Each thread holds at most EPT of the nb * W elements (blockDim.x * EPT
-  // >= nb * W, as the LDS FFT needs): unrolled, so the list and data loads of
-  // its elements are in flight together.  The first two entries of each list
-  // are read with its count (the lists are kFoldStride > 2 ints long) and
-  // used only below the count (the table has kFoldStride rows).
+  T s0[EPT], s1[EPT];
 #pragma unroll
   for (int it = 0; it < EPT; ++it) {
     const int idx = threadIdx.x + it * blockDim.x;
+    s0[it] = s1[it] = T(0);
     if (idx < nb * W) {
       const int rr = (int)fW.div(idx), c = idx - rr * W;
-      const gptr<const int> rl = frow + (row0 + rr);   // [kFoldStride][H]
-      const gptr<const int> cl = fcol + c;             // [kFoldStride][W]
-      const int nr = rl[0], nc = cl[0];
-      const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[W], c1e = cl[2 * W];
-      T s0 = T(0), s1 = T(0);
-      for (int i = 0; i < nr; ++i) {
-        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[(size_t)(1 + i) * H]);
-        const int tr = ri >> kFoldShift, er = ri & kFoldMask;
-        for (int j = 0; j < nc; ++j) {
-          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[(size_t)(1 + j) * W]);
-          const size_t tile = (size_t)tr * a.g.ntc + (cj >> kFoldShift);
-          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & kFoldMask);
-          s0 += acc[off];
-          if (has1) s1 += acc[off + plane];
-        }
-      }
-      stc(buf + idx, C2<T>{s0, s1});
+      fold_gather(acc, frow + (row0 + rr), fcol + c, H, W, a.g, a.K, k0, has1, s0[it], s1[it]);
     }
+  }
+#pragma unroll
+  for (int it = 0; it < EPT; ++it) {
+    const int idx = threadIdx.x + it * blockDim.x;
+    if (idx < nb * W) stc(buf + idx, C2<T>{s0[it], s1[it]});
   }
   __syncthreads();
   fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, tab, tw, false);

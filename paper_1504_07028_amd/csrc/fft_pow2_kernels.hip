@@ -33,41 +33,27 @@ __global__ void __launch_bounds__(p2_max_threads<T>()) fft_rows_fwd_p2_kernel(co
   const bool active = r < H;
   const int k0 = 2 * m, k1 = 2 * m + 1;
   const bool has1 = k1 < a.K;
-  const size_t plane = (size_t)a.g.ER * a.g.EC;
   const gptr<const T> acc = glob(a.acc);
   const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   const int row0 = (bid - m * nrb) * rpb;
   const int nb = min(rpb, H - row0);
   lptr<C2<T>> lds = (lptr<C2<T>>)smem;
-  // Fold: right-hand side = sum of the grown-tile partial sums covering
-  // (r, c), from the fold lists [kFoldStride][n] (count, entries), into each
-  // row's LDS region.  The workgroup's nb * N elements are 16 per thread;
-  // the loop is unrolled and each list's first two entries are read with its
-  // count, so the list and data loads of a thread's elements are in flight
-  // together (most pixels have one or two entries per direction).
+  // Fold (fold_gather): right-hand side = sum of the grown-tile partial sums
+  // covering (r, c), 16 elements per thread gathered into registers first
+  // (their loads in flight together), then stored to each row's LDS region.
+  T s0[16], s1[16];
 #pragma unroll
   for (int it = 0; it < 16; ++it) {
     const int idx = threadIdx.x + it * blockDim.x;
     const int rr = idx >> F::LG, c = idx & (N - 1);
-    if (rr < nb) {
-      const gptr<const int> rl = frow + (row0 + rr);
-      const gptr<const int> cl = fcol + c;
-      const int nr = rl[0], nc = cl[0];
-      const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[N], c1e = cl[2 * N];
-      T s0 = T(0), s1 = T(0);
-      for (int i = 0; i < nr; ++i) {
-        const int ri = i == 0 ? r0e : (i == 1 ? r1e : rl[(size_t)(1 + i) * H]);
-        const int tr = ri >> kFoldShift, er = ri & kFoldMask;
-        for (int j = 0; j < nc; ++j) {
-          const int cj = j == 0 ? c0e : (j == 1 ? c1e : cl[(size_t)(1 + j) * N]);
-          const size_t tile = (size_t)tr * a.g.ntc + (cj >> kFoldShift);
-          const size_t off = ((tile * a.K + k0) * plane) + (size_t)er * a.g.EC + (cj & kFoldMask);
-          s0 += acc[off];
-          if (has1) s1 += acc[off + plane];
-        }
-      }
-      stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0, s1});
-    }
+    s0[it] = s1[it] = T(0);
+    if (rr < nb) fold_gather(acc, frow + (row0 + rr), fcol + c, H, N, a.g, a.K, k0, has1, s0[it], s1[it]);
+  }
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int idx = threadIdx.x + it * blockDim.x;
+    const int rr = idx >> F::LG, c = idx & (N - 1);
+    if (rr < nb) stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0[it], s1[it]});
   }
   __syncthreads();
   C2<T> v[16];

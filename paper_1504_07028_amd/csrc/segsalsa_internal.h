@@ -123,6 +123,56 @@ __host__ __device__ inline int fold_list(const TileGeom& g, int x, bool is_row, 
   return cnt;
 }
 
+// Right-hand side of pixel (r, c), classes k0 and k0 + 1 (has1): the sum of
+// the grown-tile partial sums acc[tile][K][ER][EC] covering it, from the fold
+// lists rl = frow + r ([kFoldStride][H]) and cl = fcol + c ([kFoldStride][W],
+// stride W).  A pixel is almost always covered by at most two tiles per
+// direction, so the first 2 x 2 entries are gathered with predicated loads
+// whose addresses depend only on the lists (a caller unrolling over several
+// pixels gets all their list loads, then all their partial-sum loads, in
+// flight together); longer lists (tiles narrower than the halo) add the
+// remaining entries in a loop.  Terms are added row entry by row entry.
+template <typename T>
+__device__ __forceinline__ void fold_gather(__attribute__((address_space(1))) const T* acc,
+                                            __attribute__((address_space(1))) const int* rl,
+                                            __attribute__((address_space(1))) const int* cl, int H, int W,
+                                            const TileGeom& g, int K, int k0, bool has1, T& s0, T& s1) {
+  const size_t plane = (size_t)g.ER * g.EC;
+  const int nr = rl[0], nc = cl[0];
+  const int r0e = rl[H], r1e = rl[2 * H], c0e = cl[W], c1e = cl[2 * W];
+  auto rbase = [&](int re) {
+    return ((size_t)(re >> kFoldShift) * g.ntc * K + k0) * plane + (size_t)(re & kFoldMask) * g.EC;
+  };
+  auto cbase = [&](int ce) { return (size_t)(ce >> kFoldShift) * K * plane + (ce & kFoldMask); };
+  const size_t rb0 = rbase(r0e), rb1 = rbase(r1e), cb0 = cbase(c0e), cb1 = cbase(c1e);
+  const bool r1 = nr > 1, c1 = nc > 1;
+  s0 = acc[rb0 + cb0];
+  s1 = has1 ? acc[rb0 + cb0 + plane] : T(0);
+  if (c1) {
+    s0 += acc[rb0 + cb1];
+    if (has1) s1 += acc[rb0 + cb1 + plane];
+  }
+  if (r1) {
+    s0 += acc[rb1 + cb0];
+    if (has1) s1 += acc[rb1 + cb0 + plane];
+    if (c1) {
+      s0 += acc[rb1 + cb1];
+      if (has1) s1 += acc[rb1 + cb1 + plane];
+    }
+  }
+  if (nr > 2 || nc > 2) {
+    for (int i = 0; i < nr; ++i) {
+      const size_t rbi = rbase(rl[(size_t)(1 + i) * H]);
+      for (int j = 0; j < nc; ++j) {
+        if (i < 2 && j < 2) continue;
+        const size_t off = rbi + cbase(cl[(size_t)(1 + j) * W]);
+        s0 += acc[off];
+        if (has1) s1 += acc[off + plane];
+      }
+    }
+  }
+}
+
 // Workgroups of a launch are dealt to the eight XCDs of the chip round-robin
 // (workgroup i runs on XCD i mod 8), and each XCD has its own L2.  Kernels
 // whose neighbouring work items share cache lines (the halos of adjacent
