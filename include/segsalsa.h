@@ -326,7 +326,11 @@ typedef struct {
   int32_t col_dft;               /* 1: the column pass by DFTs (column DFT, symbol, inverse DFT); 0: by
                                     the exact periodic tridiagonal recursions per column frequency,
                                     cols_per_block columns of ceil(H / 32) (FP64: ceil(H / 16)) threads
-                                    each, col_threads >= their product                                 */
+                                    each, col_threads >= their product.  FP32 solves whose weights put
+                                    the recursions' largest rho = 2 Wsum / (a + sqrt(a^2 - 4 Wsum^2)),
+                                    a = 3 + 2 Wsum, within 0.1 of 1 (Wsum above ~280) take the DFT pass
+                                    whatever this field says (the recursions' rounding grows like
+                                    eps / (1 - rho)), and then ignore a tuned recursion blocking       */
   int32_t rows_per_block;        /* rows per workgroup of the row DFT passes (> 0), or 0               */
   int32_t row_threads;           /* threads per row workgroup, a multiple of 64 in [64, 1024], or 0    */
   int32_t cols_per_block;        /* columns per workgroup of the column pass (> 0), or 0               */

@@ -100,6 +100,7 @@ FftPlanDev make_fft_plan(int N) {
 }
 
 constexpr int kTriThreads = 512;   // workgroup size of the tridiagonal column pass (see plan_with)
+constexpr double kTriMinGap = 0.1;  // smallest 1 - rho of an FP32 solve by the recursions (see plan_with)
 
 // Lengths the fixed-structure engine runs: powers of two 64 .. 4096, and
 // lengths taking Bluestein whose convolution length is in that range.
@@ -488,7 +489,21 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     p.row_ept = ept;
     p.row_lds = lds_of(rpb);
   }
-  p.col_tri = !tn.col_dft;
+  // The recursions' FP32 rounding grows like eps / (1 - rho): at the largest
+  // rho (kx = 0), 1 - rho falls below kTriMinGap once Wsum exceeds ~300, and
+  // FP32 solves with such weights take the DFT column pass, whose error does
+  // not depend on rho.
+  double wsum = 0.0;
+  for (int j = 0; j < c.L; ++j) {
+    const double cj = c.fp64 ? c.w[j] : (double)(float)c.w[j];
+    wsum += cj * cj;
+  }
+  const double a0 = 3.0 + 2.0 * wsum;
+  const double rho0 = 2.0 * wsum / (a0 + std::sqrt(std::max(a0 * a0 - 4.0 * wsum * wsum, 0.0)));
+  p.col_tri = !tn.col_dft && (c.fp64 || 1.0 - rho0 >= kTriMinGap);
+  // a tuned column blocking is for the pass it names: kept for that pass only
+  const bool col_tuned = p.col_tri || tn.col_dft;
+  const int col_cpb = col_tuned ? tn.cols_per_block : 0, col_thr = col_tuned ? tn.col_threads : 0;
   if (p.col_tri) {
     // The tridiagonal recursions: lpt rows per thread, ceil(H / lpt) threads
     // per column; about 512 threads of adjacent columns per workgroup (fewer
@@ -497,8 +512,8 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     const int lpt = p.fp64 ? 16 : 32;
     const int tpc = ceil_div(H, lpt);
     long long cb;
-    if (tn.cols_per_block > 0) {
-      cb = std::min<long long>(tn.cols_per_block, W);
+    if (col_cpb > 0) {
+      cb = std::min<long long>(col_cpb, W);
     } else {
       cb = std::max(1, kTriThreads / tpc);
       if (!batch) {
@@ -507,8 +522,8 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
       }
     }
     const long long need = cb * tpc;
-    long long thr = tn.col_threads > 0 ? tn.col_threads
-                    : batch && tn.cols_per_block <= 0 && need <= kTriThreads ? kTriThreads
+    long long thr = col_thr > 0 ? col_thr
+                    : batch && col_cpb <= 0 && need <= kTriThreads ? kTriThreads
                                                                              : (need + 63) / 64 * 64;
     if (thr < need || thr > kFftMaxThreads)
       return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld columns of %d chunks need %lld threads (%lld given, at most %d)", cb,
@@ -522,7 +537,7 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   } else if (p.col_p2) {
     const int tpt = p.col_p2 / 16;
     // default: about 512 threads (FP64: 256), at least one wavefront, one workgroup per CU when there are the columns
-    long long cb = tn.cols_per_block > 0 ? std::min<long long>(tn.cols_per_block, W)
+    long long cb = col_cpb > 0 ? std::min<long long>(col_cpb, W)
                    : batch               ? std::max(1, (p.fp64 ? 256 : 512) / tpt)
                                          : std::min<long long>(W, std::max<long long>(std::max(1, 64 / tpt),
                                                                                      std::min<long long>((p.fp64 ? 256 : 512) / tpt,
@@ -531,7 +546,7 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     const long long thr = cb * tpt;
     const size_t lds = (size_t)cb * p2_region(p.col_p2) * cs;
     const int maxthr_col = p.col_blu ? kFftNarrowThreads : maxthr_p2;   // the Bluestein column kernel's bound
-    if (thr > maxthr_col || lds > kLdsBudget || (tn.col_threads > 0 && tn.col_threads != thr))
+    if (thr > maxthr_col || lds > kLdsBudget || (col_thr > 0 && col_thr != thr))
       return fail(SEGSALSA_ERR_UNSUPPORTED,
                   "%lld columns of %d per workgroup (%lld threads, %zu bytes of LDS) do not fit", cb, H, thr, lds);
     p.cols_per_block = (int)cb;
@@ -545,8 +560,8 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
     };
     long long cb;
     const int cbudget = 4096;   // elements per workgroup of a batch's uniform column shape
-    if (tn.cols_per_block > 0) {
-      cb = std::min<long long>(tn.cols_per_block, W);
+    if (col_cpb > 0) {
+      cb = std::min<long long>(col_cpb, W);
     } else {
       cb = 1;
       const long long cmax = p.fp64 ? 8 : 16;   // 128-byte runs
@@ -559,11 +574,11 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
       return fail(SEGSALSA_ERR_UNSUPPORTED, "%lld columns of %d per FFT workgroup do not fit", cb, H);
     const long long items = cb * Lc;
     // in a batch, every column workgroup within the budget has the same shape
-    const bool uniform = batch && tn.col_threads <= 0 && items <= cbudget;
-    int thr = tn.col_threads > 0 ? tn.col_threads : uniform ? cbudget / 8 : fft_threads_for(items, 8);
+    const bool uniform = batch && col_thr <= 0 && items <= cbudget;
+    int thr = col_thr > 0 ? col_thr : uniform ? cbudget / 8 : fft_threads_for(items, 8);
     int ept = uniform ? 8 : fft_ept(items, thr);
     if (ept == 0) {
-      if (tn.col_threads > 0)
+      if (col_thr > 0)
         return fail(SEGSALSA_ERR_UNSUPPORTED, "%d column threads hold at most 16 of %lld elements each", thr, items);
       thr = fft_threads_for(items, kFftEptMax);
       ept = fft_ept(items, thr);

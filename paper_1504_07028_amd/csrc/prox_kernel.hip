@@ -39,11 +39,21 @@ namespace segsalsa {
 // loads of a step only start once the previous step's work is done, so the
 // memory and the arithmetic of a step never overlap.  It doubles the per-lane
 // state, hence fewer (and fuller) wavefronts.
+//
+// SY (streamed Y, patches of 9x9 and larger): the 2L values of Y = J z - d2
+// of a pixel and class are not kept in registers between the structure-tensor
+// sums and the update; the update phase rebuilds each offset's pair from z in
+// LDS and the old d2 (read again, just before its new value overwrites it).
+// The registers then do not grow with L, so these patches keep the wavefront
+// count and the ordered FP32 scatter of the smaller ones, at the price of a
+// second read of d2 (mostly served by the caches).
 template <typename T, int M, int KPW, bool VAR, bool PF>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW, PF>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
   constexpr int L = D * D;
+  constexpr bool SY = prox_streams_y<M>();
+  constexpr int LY = SY ? 1 : L;
   const int blk = xcd_block();   // neighbouring tiles (shared halo rows) on one XCD
   const ProxArgs<T>& a = descs[find_desc(descs, ndesc, blk)];
   const TileGeom& g = a.g;
@@ -146,7 +156,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     const int lc = valid ? f - lr * tw : 0;
     const size_t stepbase = ((size_t)tile * g.steps + s) * K;
 
-    T Y[KPW][L][2];
+    T Y[KPW][LY][2];
     T pk[KPW], v1[KPW], v3[KPW], v4[KPW];
     T ps = T(0), pq = T(0), psv = T(0), pa = T(0), pb = T(0), pc = T(0);
 #pragma unroll
@@ -192,8 +202,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
           }
           const T yh = a.c[j] * (z01 - z00) - dd.x;
           const T yv = a.c[j] * (z10 - z00) - dd.y;
-          Y[kk][j][0] = yh;
-          Y[kk][j][1] = yv;
+          if constexpr (!SY) {
+            Y[kk][j][0] = yh;
+            Y[kk][j][1] = yv;
+          }
           pa += yh * yh;
           pb += yh * yv;
           pc += yv * yv;
@@ -294,6 +306,9 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
           rp_acc += e1 * e1 + e3 * e3 + e4 * e4;
         }
         const gptr<T> d2o = gd2 + 2 * (kb * (size_t)(L * 64) + lane);
+        // SY: the old d2 and z of this pixel and class, to rebuild Y offset by offset
+        [[maybe_unused]] const gptr<const T> d2i = gd2_in + 2 * (kb * (size_t)(L * 64) + lane);
+        [[maybe_unused]] const T* zk0 = zt + k * plane + (lr + M) * EC + (lc + M);
         // New d2 = u2 - Y = Y (N - I) and the J^T scatter of c_j (u2 + d2).
         // The h part of offset (dy, dx) lands at (dy, dx + 1) with + and at
         // (dy, dx) with -, the v part at (dy + 1, dx) with + and at (dy, dx)
@@ -317,7 +332,15 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
             T ah = T(0), av = T(0);
             if (in0) {
               const int jj = (da + M) * D + (db + M);
-              const T yh = Y[kk][jj][0], yv = Y[kk][jj][1];
+              T yh, yv;
+              if constexpr (SY) {   // Y of this offset again, from z in LDS and the old d2
+                const T* zr = zk0 + da * EC + db;
+                yh = a.c[jj] * (zr[1] - zr[0]) - d2i[jj * 128];
+                yv = a.c[jj] * (zr[EC] - zr[0]) - d2i[jj * 128 + 1];
+              } else {
+                yh = Y[kk][jj][0];
+                yv = Y[kk][jj][1];
+              }
               const T nh = yh * m11 + yv * m12;
               const T nv = yh * m12 + yv * m22;
               C2<T> o;
@@ -343,14 +366,12 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
               if (in0) gsum -= ah + av;
               if (inh) gsum += hprev;
               if (inv) gsum += vprev[q];
-              if constexpr (sizeof(T) == 4 && M <= 3) {
+              if constexpr (sizeof(T) == 4 && (M <= 3 || SY)) {
                 volatile __attribute__((address_space(3))) T* at =
                     (volatile __attribute__((address_space(3))) T*)(ak + da * EC + db);
                 *at = *at + gsum;
               } else {
-                // FP64: the LDS atomic add is fast and keeps register pressure
-                // down; FP32 9x9 / 11x11 patches: the ordered read-modify-write
-                // does not compile at their register pressure.
+                // FP64: the LDS atomic add is fast and keeps register pressure down.
                 atomicAdd(ak + da * EC + db, gsum);
               }
             }

@@ -5,13 +5,23 @@
 
 namespace segsalsa {
 
+// Patches of 9x9 and larger rebuild Y = J z - d2 in the prox kernel's update
+// phase instead of keeping it in registers.
+template <int M>
+__host__ __device__ constexpr bool prox_streams_y() {
+  return M >= 4;
+}
+
 // Largest workgroup the prox kernel instantiation <T, M, KPW> is compiled for:
 // each lane keeps KPW classes x 2L entries of the J-split block in registers,
 // so the wavefronts per SIMD (and hence per workgroup) shrink as L grows.
 template <typename T, int M, int KPW, bool PF = false>
 __host__ __device__ constexpr int prox_max_threads() {
   constexpr int L = (2 * M + 1) * (2 * M + 1);
-  constexpr int vg = (PF ? 2 : 1) * KPW * 2 * L * (int)(sizeof(T) / 4) + (PF ? 56 : 48);
+  // registers held per class: Y's 2L values, or (patches of 9x9 and larger,
+  // which rebuild Y in the update phase) the carries of the scatter
+  constexpr int LY = prox_streams_y<M>() ? 2 * M + 2 : L;
+  constexpr int vg = (PF ? 2 : 1) * KPW * 2 * LY * (int)(sizeof(T) / 4) + (PF ? 56 : 48);
   constexpr int wps = 512 / vg;
   constexpr int w = wps >= 4 ? 4 : (wps < 1 ? 1 : wps);
   return w * 4 * 64;

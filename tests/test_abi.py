@@ -370,6 +370,17 @@ def test_prefetch_entries_only_where_built(clean_table):
         assert e.value.status == UNSUPPORTED
 
 
+def test_fp32_column_pass_follows_the_weights(S):
+    """The column recursions' FP32 rounding grows like eps / (1 - rho) at the largest rho (kx = 0), so
+    FP32 solves whose weights put rho within 0.1 of 1 (Wsum above ~280) plan the DFT column pass; FP64
+    keeps the recursions at any weights."""
+    imgs, _ = S.image_table([(4, 96, 128)], [1.0], [1.0])
+    for scale, prec, want in ((1.0, 0, 0), (250.0 ** 0.5, 0, 0), (300.0 ** 0.5, 0, 1), (100.0, 0, 1), (100.0, 1, 0)):
+        params = S.BatchParams(1, [scale / 3] * 9, 1.0, 10)   # Wsum = scale ** 2
+        (plan,) = S.segsalsa_str_batch_plans(imgs, params, prec)
+        assert plan["col_dft"] == want, (scale, prec, plan)
+
+
 def test_batch_plans_depend_on_transform_length_only(S):
     """In a batch of several images the FFT blocking is a function of the transform length, so images
     of one length share a launch: equal column lengths (211 and 227 both take Bluestein over 512

@@ -159,6 +159,27 @@ def test_small_grids_engine_forced(H, W, K, M, p, iters, dtype):
     check_err(err, dtype)
 
 
+# the column recursions across the range of Wsum = sum c_j^2: rho = 0 (no patch weights: the prior
+# vanishes and the solve is z = rhs / 3), the largest rho FP32 solves take them at (Wsum = 256:
+# 1 - rho = 0.103), rho near 1 (Wsum = 1e4: the periodic closure carries the column; FP64 only, FP32
+# plans the DFT pass there), and a column length with a short last chunk (H = 70: 32 + 32 + 6)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("scale", [0.0, 10.0, 16.0, 100.0])
+def test_column_recursions_across_weight_scales(scale, dtype):
+    S = need_gpu()
+    H, W, K, M, iters = 70, 45, 3, 1, 5
+    probs, _, _, c = problem_inputs(H, W, K, M, seed=900 + int(scale))
+    c = np.asarray(c) * scale
+    say(f"case weights x{scale} (Wsum = {float(np.sum(c ** 2)):.3g}) {dtype}")
+    z, *_ = gpu_solve(S, probs, c, M, 1.0, 0.6, 1.2, iters, dtype)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, 1.0, 0.6, 1.2, iters)
+    err = float(np.max(np.abs(z.double().cpu().numpy() - zo)))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    # (FP32 at Wsum = 1e4 plans the DFT column pass: 1 - rho = 0.017 there, and the recursions' FP32
+    # rounding grows like eps / (1 - rho): 2.3e-5 against the DFT pass's 3.7e-6 on this case)
+    check_err(err, dtype)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
 def test_plain_64x64(dtype):
     """The 64x64, K = 4, 3x3 patch, Schatten-1, 100-round workload."""
