@@ -601,7 +601,8 @@ segsalsa_status plan_with(int K, int H, int W, const Common& c, const segsalsa_t
   p.off_phat = off; off = align_up(off + nt * p.g.steps * per_step);
   p.off_dm = off; off = align_up(off + nt * p.g.steps * per_step * 3);
   p.off_d2 = off; off = align_up(off + nt * p.g.steps * per_step * 2 * p.L);
-  p.off_acc = off; off = align_up(off + nt * (size_t)K * p.g.ER * p.g.EC * p.ts);
+  off += kAccGuard;   // guard bands: the vector fold's masked loads reach a few elements beyond the partial sums
+  p.off_acc = off; off = align_up(off + nt * (size_t)K * p.g.ER * p.g.EC * p.ts + kAccGuard);
   p.off_spec = off; off = align_up(off + (size_t)p.P * H * W * cs);
   p.off_zprev = off; off = align_up(off + (size_t)K * H * W * p.ts);
   p.off_restile = off; off = align_up(off + nt * 8);
@@ -912,6 +913,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     f.K = p.K;
     f.P = p.P;
     f.rows_per_block = p.rows_per_block;
+    f.vfold = p.W % p.g.ntc == 0 && p.g.TC % kFoldVec<T> == 0 && p.g.TC >= 2 * p.M + 2;
     f.acc = wsp<T>(base, p.off_acc);
     f.frow = wsp<int>(base, p.off_frow);
     f.fcol = wsp<int>(base, p.off_fcol);
@@ -1440,7 +1442,7 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
   if ((s = make_batch(1, &pr->K, &pr->H, &pr->W, &pr->lambda, &pr->mu, c, gl.b)) != SEGSALSA_OK) return s;
   const Plan& p = gl.b.im[0].plan;
   gl.zbytes = align_up((size_t)p.K * p.H * p.W * p.ts);
-  gl.sbytes = p.off_acc - p.off_dm;
+  gl.sbytes = p.off_acc - kAccGuard - p.off_dm;
   if (every_ck == 0) every_ck = auto_interval(c.iters, gl.zbytes + gl.sbytes);
   gl.S = std::max(1, std::min(every_ck, std::max(1, c.iters)));
   gl.nck = c.iters == 0 ? 1 : ceil_div(c.iters, gl.S);
@@ -1451,7 +1453,8 @@ segsalsa_status make_grad_layout(const segsalsa_problem* pr, segsalsa_precision 
   gl.off_r = off; off = align_up(off + gl.zbytes);
   gl.off_bst = off; off = align_up(off + gl.sbytes);
   gl.off_pbar = off; off = align_up(off + (p.off_dm - p.off_phat));
-  gl.off_bacc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts);
+  off += kAccGuard;
+  gl.off_bacc = off; off = align_up(off + nt * (size_t)p.K * p.g.ER * p.g.EC * p.ts + kAccGuard);
   gl.off_gpart = off; off = align_up(off + nt * (size_t)(p.L + 2) * 8);
   gl.off_gtot = off; off = align_up(off + (size_t)(p.L + 2) * 8);
   gl.off_ck = off; off = align_up(off + (size_t)gl.nck * (gl.zbytes + gl.sbytes));

@@ -95,33 +95,10 @@ __global__ void __launch_bounds__(p2_max_threads<T>()) fft_rows_fwd_blu_kernel(c
   const int nb = min(rpb, H - row0);
   const int k0 = 2 * m, k1 = 2 * m + 1;
   const bool has1 = k1 < a.K;
-  const gptr<const T> acc = glob(a.acc);
-  const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   lptr<C2<T>> lds = (lptr<C2<T>>)smem;
-  // Fold (fold_gather): right-hand side = sum of the grown-tile partial sums
-  // covering (r, c); the workgroup's nb * W elements are at most 8 per thread
-  // (W <= MM / 2), gathered into registers first (their loads in flight
-  // together), then stored to each row's LDS region.
-  const FastDiv fW(W);
-  const int nel = nb * W;
-  T s0[8], s1[8];
-#pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    s0[it] = s1[it] = T(0);
-    if (idx < nel) {
-      const int rr = (int)fW.div(idx), c = idx - rr * W;
-      fold_gather(acc, frow + (row0 + rr), fcol + c, H, W, a.g, a.K, k0, has1, s0[it], s1[it]);
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    if (idx < nel) {
-      const int rr = (int)fW.div(idx), c = idx - rr * W;
-      stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0[it], s1[it]});
-    }
-  }
+  // Fold (fold_rows): the workgroup's nb * W elements are at most 8 per
+  // thread (W <= MM / 2), stored to each row's LDS region
+  fold_rows<T, 8>(a, row0, nb, k0, has1, [&](int rr, int c, C2<T> x) { stc(lds + rr * F::REGION + F::pad(c), x); });
   __syncthreads();
   C2<T> v[16];
 #pragma unroll

@@ -367,29 +367,10 @@ __global__ void __launch_bounds__(MAXT) fft_rows_fwd_kernel(const RowFwdArgs<T>*
   const FftTab<T>& tab = a.tab;
   if (!a.plan.blu)
     for (int t = threadIdx.x; t < W; t += blockDim.x) stc(tw + t, ldc(glob(tab.tw) + t));
-  const gptr<const T> acc = glob(a.acc);
-  const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
-  // right-hand side = sum of the grown-tile partial sums covering (r, c)
-  // (fold_gather).  Each thread holds at most EPT of the nb * W elements
-  // (blockDim.x * EPT >= nb * W, as the LDS FFT needs), gathered into
-  // registers first so that their loads are in flight together.
+  // right-hand side (fold_rows): each thread holds at most EPT of the nb * W
+  // elements (blockDim.x * EPT >= nb * W, as the LDS FFT needs)
   const bool has1 = k1 < a.K;
-  const FastDiv fW(W);
-  T s0[EPT], s1[EPT];
-#pragma unroll
-  for (int it = 0; it < EPT; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    s0[it] = s1[it] = T(0);
-    if (idx < nb * W) {
-      const int rr = (int)fW.div(idx), c = idx - rr * W;
-      fold_gather(acc, frow + (row0 + rr), fcol + c, H, W, a.g, a.K, k0, has1, s0[it], s1[it]);
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < EPT; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    if (idx < nb * W) stc(buf + idx, C2<T>{s0[it], s1[it]});
-  }
+  fold_rows<T, EPT>(a, row0, nb, k0, has1, [&](int rr, int c, C2<T> x) { stc(buf + rr * W + c, x); });
   __syncthreads();
   fft_lds<T, EPT>(buf, a.plan, nb, 1, W, tw, tab, tw, false);
   const gptr<C2<T>> out = glob(a.spec) + ((size_t)m * H + row0) * W;

@@ -26,6 +26,64 @@ __device__ __forceinline__ void stc(P p, const V& v) {
   p->y = v.y;
 }
 
+// Fold of a row workgroup: the right-hand side of rows row0 .. row0 + nb - 1
+// (classes k0 and k0 + 1) from the grown-tile partial sums, handed to
+// store(rr, c, value) for every element (rr: row within the workgroup).
+// Thread i takes elements i, i + blockDim, ... (at most EPT of them; blockDim
+// EPT >= nb W), all gathered into registers before the first store so that
+// their loads are in flight together.  With a.vfold, groups of kFoldVec<T>
+// adjacent columns (fold_gather_vec; W is then a multiple of the group),
+// element by element (fold_gather) otherwise.
+template <typename T, int EPT, typename Store>
+__device__ __forceinline__ void fold_rows(const RowFwdArgs<T>& a, int row0, int nb, int k0, bool has1, Store store) {
+  const gptr<const T> acc = glob(a.acc);
+  const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
+  const int H = a.g.H, W = a.g.W;
+  const FastDiv fW(W);
+  const int nel = nb * W;
+  if (a.vfold) {
+    constexpr int V = kFoldVec<T>;
+    constexpr int NG = (EPT + V - 1) / V;
+    T s0[NG * V], s1[NG * V];
+#pragma unroll
+    for (int it = 0; it < NG; ++it) {
+      const int idx = (threadIdx.x + it * blockDim.x) * V;
+      if (idx < nel) {
+        const int rr = (int)fW.div(idx), c = idx - rr * W;
+        fold_gather_vec(acc, frow + (row0 + rr), H, c, a.g, a.K, k0, has1, s0 + it * V, s1 + it * V);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NG; ++it) {
+      const int idx = (threadIdx.x + it * blockDim.x) * V;
+      if (idx < nel) {
+        const int rr = (int)fW.div(idx), c = idx - rr * W;
+#pragma unroll
+        for (int j = 0; j < V; ++j) store(rr, c + j, C2<T>{s0[it * V + j], s1[it * V + j]});
+      }
+    }
+  } else {
+    T s0[EPT], s1[EPT];
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      s0[it] = s1[it] = T(0);
+      if (idx < nel) {
+        const int rr = (int)fW.div(idx), c = idx - rr * W;
+        fold_gather(acc, frow + (row0 + rr), fcol + c, H, W, a.g, a.K, k0, has1, s0[it], s1[it]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      if (idx < nel) {
+        const int rr = (int)fW.div(idx), c = idx - rr * W;
+        store(rr, c, C2<T>{s0[it], s1[it]});
+      }
+    }
+  }
+}
+
 template <typename T>
 __device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>

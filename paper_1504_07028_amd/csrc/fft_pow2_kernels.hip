@@ -33,28 +33,12 @@ __global__ void __launch_bounds__(p2_max_threads<T>()) fft_rows_fwd_p2_kernel(co
   const bool active = r < H;
   const int k0 = 2 * m, k1 = 2 * m + 1;
   const bool has1 = k1 < a.K;
-  const gptr<const T> acc = glob(a.acc);
-  const gptr<const int> frow = glob(a.frow), fcol = glob(a.fcol);
   const int row0 = (bid - m * nrb) * rpb;
   const int nb = min(rpb, H - row0);
   lptr<C2<T>> lds = (lptr<C2<T>>)smem;
-  // Fold (fold_gather): right-hand side = sum of the grown-tile partial sums
-  // covering (r, c), 16 elements per thread gathered into registers first
-  // (their loads in flight together), then stored to each row's LDS region.
-  T s0[16], s1[16];
-#pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    const int rr = idx >> F::LG, c = idx & (N - 1);
-    s0[it] = s1[it] = T(0);
-    if (rr < nb) fold_gather(acc, frow + (row0 + rr), fcol + c, H, N, a.g, a.K, k0, has1, s0[it], s1[it]);
-  }
-#pragma unroll
-  for (int it = 0; it < 16; ++it) {
-    const int idx = threadIdx.x + it * blockDim.x;
-    const int rr = idx >> F::LG, c = idx & (N - 1);
-    if (rr < nb) stc(lds + rr * F::REGION + F::pad(c), C2<T>{s0[it], s1[it]});
-  }
+  // Fold (fold_rows): 16 elements per thread, stored to each row's LDS region
+  fold_rows<T, 16>(a, row0, nb, k0, has1,
+                   [&](int rr, int c, C2<T> x) { stc(lds + rr * F::REGION + F::pad(c), x); });
   __syncthreads();
   C2<T> v[16];
 #pragma unroll

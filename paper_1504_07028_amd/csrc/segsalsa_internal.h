@@ -173,6 +173,81 @@ __device__ __forceinline__ void fold_gather(__attribute__((address_space(1))) co
   }
 }
 
+// Fold of kFoldVec<T> = 16 / sizeof(T) adjacent columns c .. c + kFoldVec - 1
+// of one row, for tile geometries where every tile column is tw = W / ntc
+// wide, tw a multiple of kFoldVec and tw >= 2M + 2 (a column is then covered
+// by its own tile and at most one neighbour, and the group lies in one tile
+// column).  Column x = c0 + x0 + j of tile column tc sits at grown position
+// x0 + j + M of tile tc; at tw + M + x0 + j of tile tc - 1 when x0 + j <= M;
+// at x0 + j - tw + M of tile tc + 1 when x0 + j >= tw - M (tile columns
+// taken periodically).  Each term of a row entry is one 16-byte load per
+// class; components outside a neighbour's range are dropped by selection
+// (their loads reach at most kFoldVec - 1 elements before or after a grown
+// row, inside the guard bands around the partial sums).  Row entries come
+// from the row list as in fold_gather; the sums are exact per component in
+// the same order as fold_gather's (row entry by row entry, own tile column
+// before the neighbour).
+template <typename T>
+constexpr int kFoldVec = 16 / (int)sizeof(T);
+constexpr size_t kAccGuard = 256;   // bytes of guard band before and after the partial sums
+
+template <typename T>
+struct FoldVec {
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T)), aligned(sizeof(T))));
+};
+
+template <typename T>
+__device__ __forceinline__ void fold_gather_vec(__attribute__((address_space(1))) const T* acc,
+                                                __attribute__((address_space(1))) const int* rl, int H, int c,
+                                                const TileGeom& g, int K, int k0, bool has1, T* s0, T* s1) {
+  constexpr int V = kFoldVec<T>;
+  using VT = typename FoldVec<T>::type;
+  const size_t plane = (size_t)g.ER * g.EC;
+  const int M = g.M, tw = g.TC;
+  const int tc = c / tw, x0 = c - tc * tw;
+  const bool left = x0 <= M, right = x0 + V - 1 >= tw - M;
+  const int tl = tc == 0 ? g.ntc - 1 : tc - 1, tr = tc + 1 == g.ntc ? 0 : tc + 1;
+  const long long co = (long long)tc * K * plane + x0 + M;
+  const long long cl = (long long)tl * K * plane + tw + M + x0;
+  const long long cr = (long long)tr * K * plane + x0 - tw + M;
+  const int nr = rl[0];
+  auto rbase = [&](int re) {
+    return (long long)(((size_t)(re >> kFoldShift) * g.ntc * K + k0) * plane + (size_t)(re & kFoldMask) * g.EC);
+  };
+  auto ld = [&](long long off) { return *(__attribute__((address_space(1))) const VT*)(acc + off); };
+  // terms in column order (the neighbour on the left, the own tile, the
+  // neighbour on the right), the first row entry's starting the sum
+  auto add = [&](T* s, long long rb, bool first) {
+    const VT o = ld(rb + co);
+    const VT l = left ? ld(rb + cl) : VT(0);
+    const VT r = right ? ld(rb + cr) : VT(0);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const bool uj = left && x0 + j <= M, vj = right && x0 + j >= tw - M;
+      T t;
+      if (first) t = uj ? l[j] + o[j] : o[j];
+      else t = uj ? (s[j] + l[j]) + o[j] : s[j] + o[j];
+      if (vj) t += r[j];
+      s[j] = t;
+    }
+  };
+  const long long rb0 = rbase(rl[H]);
+  const long long rb1 = nr > 1 ? rbase(rl[2 * H]) : rb0;
+#pragma unroll
+  for (int j = 0; j < V; ++j) s1[j] = T(0);
+  add(s0, rb0, true);
+  if (has1) add(s1, rb0 + (long long)plane, true);
+  if (nr > 1) {
+    add(s0, rb1, false);
+    if (has1) add(s1, rb1 + (long long)plane, false);
+  }
+  for (int i = 2; i < nr; ++i) {
+    const long long rbi = rbase(rl[(size_t)(1 + i) * H]);
+    add(s0, rbi, false);
+    if (has1) add(s1, rbi + (long long)plane, false);
+  }
+}
+
 // Workgroups of a launch are dealt to the eight XCDs of the chip round-robin
 // (workgroup i runs on XCD i mod 8), and each XCD has its own L2.  Kernels
 // whose neighbouring work items share cache lines (the halos of adjacent
@@ -277,6 +352,7 @@ struct RowFwdArgs {
   TileGeom g;
   int K, P;
   int rows_per_block;
+  int vfold;                    // 1: tile columns allow fold_gather_vec
   const T* __restrict__ acc;    // per-tile partial sums
   const int* __restrict__ frow; // [kFoldStride][H] fold lists of rows
   const int* __restrict__ fcol; // [kFoldStride][W] fold lists of columns

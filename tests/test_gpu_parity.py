@@ -267,3 +267,52 @@ def test_interface_edges(H, W, K, M, p, iters, only, dtype):
     err = np.max(np.abs(z.double().cpu().numpy() - zo))
     say(f"  max|z_gpu - z_oracle| = {err:.3e}")
     check_err(err, dtype)
+
+
+# the vector fold (16-byte loads of adjacent columns of one tile column), taken when every tile column
+# has the same width, a multiple of 4 (FP32) or 2 (FP64), and at least 2M + 2: one, two and many tile
+# columns (the neighbours are then the tile itself or one other tile), M = 0 .. 3, an odd K, tiles
+# shorter than the halo (rows covered by more than two tiles), a Bluestein row length (404 = 4 x 101);
+# in the general row kernel and, by tuned blocking, on the fixed-structure engine.
+# (H, W, K, M, tile_rows, tile_cols, iters)
+VFOLD_CASES = [
+    (64, 128, 5, 1, 8, 16, 4),
+    (70, 64, 3, 2, 16, 64, 4),
+    (33, 256, 4, 3, 6, 128, 3),
+    (40, 64, 2, 0, 8, 8, 4),
+    (30, 128, 3, 3, 3, 16, 3),
+    (20, 404, 3, 1, 10, 4, 3),
+]
+
+
+def vfold_applies(W, M, tile_cols, vec):
+    ntc = -(-W // min(tile_cols, W))
+    tc = -(-W // ntc)
+    return W % ntc == 0 and tc % vec == 0 and tc >= 2 * M + 2
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("engine", [True, False], ids=["engine", "general"])
+@pytest.mark.parametrize("H,W,K,M,tr,tc,iters", VFOLD_CASES)
+def test_vector_fold(H, W, K, M, tr, tc, iters, engine, dtype):
+    S = need_gpu()
+    prec = S._prec(dtype)
+    assert vfold_applies(W, M, tc, 4 if dtype == torch.float32 else 2)
+    tn = dict(tile_rows=tr, tile_cols=tc)
+    if engine:
+        tn["rows_per_block"] = max(1, 64 // (engine_length(W) // 16))
+    else:
+        tn["generic_fft"] = 1
+    S.segsalsa_tuning_set(K, H, W, M, prec, tn)
+    try:
+        plan, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+        assert tuned and plan["generic_fft"] == (0 if engine else 1)
+        say(f"case vector fold H={H} W={W} K={K} M={M} tiles {tr}x{tc} iters={iters} {dtype}: {plan}")
+        probs, _, _, c = problem_inputs(H, W, K, M, seed=H * 17 + W + M)
+        z, *_ = gpu_solve(S, probs, c, M, 1.0, 0.8, 1.3, iters, dtype)
+    finally:
+        S.segsalsa_tuning_set(K, H, W, M, prec, None)
+    zo = oracle_solve(rounded_input(probs, dtype), weights_as_seen(c, dtype), M, 1.0, 0.8, 1.3, iters)
+    err = np.max(np.abs(z.double().cpu().numpy() - zo))
+    say(f"  max|z_gpu - z_oracle| = {err:.3e}")
+    check_err(err, dtype)
