@@ -161,6 +161,12 @@ bool fold_lists_fit(const TileGeom& g) {
   return true;
 }
 
+// Tile columns the vector fold handles (fold_gather_vec): one width, a
+// multiple of kFoldVec elements, at least 2M + 2.
+bool vector_fold_fits(const TileGeom& g, size_t ts) {
+  return g.W % g.ntc == 0 && g.TC % (int)(16 / ts) == 0 && g.TC >= 2 * g.M + 2;
+}
+
 // LDS bytes of the prox workgroup (and of the reverse sweep's, for
 // differentiable solves) on the grown tile of g.
 size_t prox_lds_fwd(const Plan& p, const TileGeom& g) {
@@ -176,8 +182,9 @@ size_t prox_lds_adj(const Plan& p, const TileGeom& g) {
 // Tile shapes that fit LDS, best first by the cost model: a workgroup
 // processes one tile in ceil(pixels / 64) steps plus a fixed load/store
 // phase and tiles run in batches of (compute units x resident workgroups),
-// so the cost is batches x (steps + 1); ties go to the smaller grown-tile
-// overhead.
+// so the cost is batches x (steps + 1); ties go to shapes whose tile columns
+// allow the vector fold (one width, a multiple of 16 bytes of elements, at
+// least 2M + 2), then to the smaller grown-tile overhead.
 std::vector<TileGeom> tile_candidates(const Plan& p) {
   static const int rows[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32};
   static const int cols[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
@@ -186,7 +193,9 @@ std::vector<TileGeom> tile_candidates(const Plan& p) {
   const int occ_regs = std::max(1, (4 * waves_per_simd) / p.nw);
   struct Cand {
     TileGeom g;
-    double cost, over;
+    double cost;
+    bool vf;
+    double over;
   };
   std::vector<Cand> cs;
   for (int tr : rows) {
@@ -200,11 +209,14 @@ std::vector<TileGeom> tile_candidates(const Plan& p) {
       const int occ = std::max(1, std::min(occ_regs, (int)(kLdsBudget / lds)));
       const long long slots = (long long)kTargetGroups * occ;
       const long long batches = (g.ntiles() + slots - 1) / slots;
-      cs.push_back({g, (double)batches * (g.steps + 1), (double)g.ER * g.EC / ((double)g.TR * g.TC)});
+      cs.push_back({g, (double)batches * (g.steps + 1), vector_fold_fits(g, p.ts),
+                    (double)g.ER * g.EC / ((double)g.TR * g.TC)});
     }
   }
   std::stable_sort(cs.begin(), cs.end(), [](const Cand& a, const Cand& b) {
-    return a.cost != b.cost ? a.cost < b.cost : a.over < b.over;
+    if (a.cost != b.cost) return a.cost < b.cost;
+    if (a.vf != b.vf) return a.vf;
+    return a.over < b.over;
   });
   std::vector<TileGeom> out;
   for (const Cand& c : cs) out.push_back(c.g);
@@ -913,7 +925,7 @@ hipError_t upload_tables(const Batch& b, void* ws, const std::vector<int>& activ
     f.K = p.K;
     f.P = p.P;
     f.rows_per_block = p.rows_per_block;
-    f.vfold = p.W % p.g.ntc == 0 && p.g.TC % kFoldVec<T> == 0 && p.g.TC >= 2 * p.M + 2;
+    f.vfold = vector_fold_fits(p.g, sizeof(T));
     f.acc = wsp<T>(base, p.off_acc);
     f.frow = wsp<int>(base, p.off_frow);
     f.fcol = wsp<int>(base, p.off_fcol);
