@@ -261,7 +261,7 @@ def test_tuning_set_get_and_workspace(clean_table):
     assert not tuned and plan["tile_rows"] > 0 and plan["row_threads"] % 64 == 0
     st, before = status_of_size(S, base_problem(S, K=K, H=H, W=W))
     assert st == OK
-    want = dict(tile_rows=5, tile_cols=12, classes_per_wave=2, prefetch=1, generic_fft=0, col_dft=0, rows_per_block=3,
+    want = dict(tile_rows=4, tile_cols=20, classes_per_wave=2, prefetch=1, generic_fft=0, col_dft=0, rows_per_block=3,
                 row_threads=128, cols_per_block=4, col_threads=192, us_per_round=12.5)
     S.segsalsa_tuning_set(K, H, W, M, 0, want)
     got, tuned = S.segsalsa_tuning_get(K, H, W, M, 0)
