@@ -397,3 +397,20 @@ def test_batch_plans_depend_on_transform_length_only(S):
     # a single image of one of these shapes is planned on its own work instead
     single, _ = S.segsalsa_tuning_get(4, 211, 300, 1, 0)
     assert single["tile_rows"] == plans[0]["tile_rows"] and single["tile_cols"] == plans[0]["tile_cols"]
+
+
+def test_planner_prefers_vector_fold_tiles(clean_table):
+    """Among tile shapes of equal cost the planner takes one whose tile columns the vector fold handles
+    (every tile column W / ntc wide, a multiple of 16 bytes of elements, at least 2M + 2): the 2048x2048
+    workload, the 256x256 one and a 40x60 image, both precisions."""
+    S = clean_table
+
+    def vector_fold_fits(W, M, tile_cols, vec):
+        ntc = -(-W // min(tile_cols, W))
+        tc = -(-W // ntc)
+        return W % ntc == 0 and tc % vec == 0 and tc >= 2 * M + 2
+
+    for K, H, W, M in ((16, 2048, 2048, 2), (8, 256, 256, 1), (4, 40, 60, 1)):
+        for prec, vec in ((0, 4), (1, 2)):
+            plan, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
+            assert not tuned and vector_fold_fits(W, M, plan["tile_cols"], vec), (K, H, W, M, prec, plan)
