@@ -47,7 +47,14 @@ namespace segsalsa {
 // The registers then do not grow with L, so these patches keep the wavefront
 // count and the ordered FP32 scatter of the smaller ones, at the price of a
 // second read of d2 (mostly served by the caches).
-template <typename T, int M, int KPW, bool VAR, bool PF>
+//
+// NT (streaming, plain instantiation only): p_hat, d1, d3, d4 and d2 are
+// loaded and stored nontemporally.  A round touches each of them once, so
+// when the state of all images of a launch far exceeds the L2s and the
+// 256 MB MALL, caching them only evicts what the next kernels read again (the
+// partial sums, z); when it fits, the cached accesses keep it resident from
+// round to round.  The host chooses per round from the state's size.
+template <typename T, int M, int KPW, bool VAR, bool PF, bool NT>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW, PF>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   constexpr int D = 2 * M + 1;
@@ -74,6 +81,16 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   const gptr<const T> gd2_in = glob(a.d2_in);   // (h, v) pairs
   const gptr<T> gdm = glob(a.dm);
   const gptr<T> gd2 = glob(a.d2);
+  // NT: the per-pixel state streams past the caches (nontemporal loads and
+  // stores), for rounds whose state is far larger than the caches
+  auto sld = [](gptr<const T> p) -> T {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+  };
+  auto sst = [](gptr<T> p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+  };
 
   extern __shared__ __align__(16) unsigned char smem[];
   T* zt = reinterpret_cast<T*>(smem);  // [K][ER][EC] z over the grown tile (periodic)
@@ -172,10 +189,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
           d3 = P3[kk];
           d4 = P4[kk];
         } else {
-          pk[kk] = gphat[kb * 64 + lane];
-          d1 = gdm_in[(kb * 3 + 0) * 64 + lane];
-          d3 = gdm_in[(kb * 3 + 1) * 64 + lane];
-          d4 = gdm_in[(kb * 3 + 2) * 64 + lane];
+          pk[kk] = sld(gphat + kb * 64 + lane);
+          d1 = sld(gdm_in + (kb * 3 + 0) * 64 + lane);
+          d3 = sld(gdm_in + (kb * 3 + 1) * 64 + lane);
+          d4 = sld(gdm_in + (kb * 3 + 2) * 64 + lane);
         }
         const T* zk = zt + k * plane + (lr + M) * EC + (lc + M);
         const T zc = zk[0];
@@ -197,8 +214,9 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
             dd.x = Pd[kk][j < LP ? j : 0][0];
             dd.y = Pd[kk][j < LP ? j : 0][1];
           } else {
-            dd.x = d2p[j * 128];
-            dd.y = d2p[j * 128 + 1];
+            // (the streamed-Y patches read d2 again in the update: cached)
+            dd.x = SY ? d2p[j * 128] : sld(d2p + j * 128);
+            dd.y = SY ? d2p[j * 128 + 1] : sld(d2p + j * 128 + 1);
           }
           const T yh = a.c[j] * (z01 - z00) - dd.x;
           const T yv = a.c[j] * (z10 - z00) - dd.y;
@@ -295,9 +313,9 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
         const T d3n = v3[kk] < T(0) ? -v3[kk] : T(0);
         const T d4n = g4s ? T(fmax((double)v4[kk] - theta, 0.0) - (double)v4[kk]) : d4a;
         const T own = (v1[kk] + T(2) * d1n) + (v3[kk] < T(0) ? -v3[kk] : v3[kk]) + (v4[kk] + T(2) * d4n);
-        gdm[(kb * 3 + 0) * 64 + lane] = d1n;
-        gdm[(kb * 3 + 1) * 64 + lane] = d3n;
-        gdm[(kb * 3 + 2) * 64 + lane] = d4n;
+        sst(gdm + (kb * 3 + 0) * 64 + lane, d1n);
+        sst(gdm + (kb * 3 + 1) * 64 + lane, d3n);
+        sst(gdm + (kb * 3 + 2) * 64 + lane, d4n);
         if (want_res) {  // primal residual: d_new - d_old = u - H z (eq. (14))
           const T zc = zt[k * plane + (lr + M) * EC + (lc + M)];
           const double e1 = (double)d1n - (double)(zc - v1[kk]);
@@ -346,8 +364,8 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
               C2<T> o;
               o.x = nh;
               o.y = nv;
-              d2o[jj * 128] = o.x;
-              d2o[jj * 128 + 1] = o.y;
+              sst(d2o + jj * 128, o.x);
+              sst(d2o + jj * 128 + 1, o.y);
               if (want_res) {  // old d2 = c_j grad z - Y, rebuilt from the LDS tile
                 const T* zr = zt + k * plane + (lr + M + da) * EC + (lc + M + db);
                 const double oh = (double)(a.c[jj] * (zr[1] - zr[0]) - yh);
@@ -405,10 +423,10 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
   }
 }
 
-template <typename T, int M, int KPW, bool VAR, bool PF>
+template <typename T, int M, int KPW, bool VAR, bool PF, bool NT = false>
 static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks, int threads, size_t lds,
                                 hipStream_t st) {
-  auto fn = prox_rhs_kernel<T, M, KPW, VAR, PF>;
+  auto fn = prox_rhs_kernel<T, M, KPW, VAR, PF, NT>;
   static bool lds_set = false;  // idempotent, so a racing second call is harmless
   if (!lds_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -421,13 +439,23 @@ static hipError_t launch_prox_t(const ProxArgs<T>* descs, int ndesc, int blocks,
 }
 
 template <typename T, int M, bool VAR>
-static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, bool pf, size_t lds,
-                                hipStream_t st) {
+static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int threads, int kpw, bool pf, bool nt,
+                                size_t lds, hipStream_t st) {
   if (pf) {   // built for the plain FP32 kernel with two classes per wavefront and M <= 2 only
     if constexpr (prox_has_prefetch<T, M, 2, VAR>()) {
       if (kpw == 2) return launch_prox_t<T, M, 2, VAR, true>(d, n, blocks, threads, lds, st);
     }
     return hipErrorInvalidValue;
+  }
+  if constexpr (!VAR) {   // the streaming build: plain instantiation only
+    if (nt) {
+      switch (kpw) {
+        case 1: return launch_prox_t<T, M, 1, false, false, true>(d, n, blocks, threads, lds, st);
+        case 2: return launch_prox_t<T, M, 2, false, false, true>(d, n, blocks, threads, lds, st);
+        case 4: return launch_prox_t<T, M, 4, false, false, true>(d, n, blocks, threads, lds, st);
+        default: return hipErrorInvalidValue;
+      }
+    }
   }
   switch (kpw) {
     case 1: return launch_prox_t<T, M, 1, VAR, false>(d, n, blocks, threads, lds, st);
@@ -439,27 +467,27 @@ static hipError_t launch_prox_m(const ProxArgs<T>* d, int n, int blocks, int thr
 
 template <typename T, bool VAR>
 static hipError_t launch_prox_v(const ProxArgs<T>* d, int n, int blocks, int threads, int M, int kpw, bool pf,
-                                size_t lds, hipStream_t st) {
+                                bool nt, size_t lds, hipStream_t st) {
   switch (M) {
-    case 0: return launch_prox_m<T, 0, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
-    case 1: return launch_prox_m<T, 1, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
-    case 2: return launch_prox_m<T, 2, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
-    case 3: return launch_prox_m<T, 3, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
-    case 4: return launch_prox_m<T, 4, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
-    case 5: return launch_prox_m<T, 5, VAR>(d, n, blocks, threads, kpw, pf, lds, st);
+    case 0: return launch_prox_m<T, 0, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
+    case 1: return launch_prox_m<T, 1, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
+    case 2: return launch_prox_m<T, 2, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
+    case 3: return launch_prox_m<T, 3, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
+    case 4: return launch_prox_m<T, 4, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
+    case 5: return launch_prox_m<T, 5, VAR>(d, n, blocks, threads, kpw, pf, nt, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
-                       bool variants, hipStream_t st) {
-  return variants ? launch_prox_v<float, true>(d, n, blocks, threads, M, kpw, pf, lds, st)
-                  : launch_prox_v<float, false>(d, n, blocks, threads, M, kpw, pf, lds, st);
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, bool nt,
+                       size_t lds, bool variants, hipStream_t st) {
+  return variants ? launch_prox_v<float, true>(d, n, blocks, threads, M, kpw, pf, nt, lds, st)
+                  : launch_prox_v<float, false>(d, n, blocks, threads, M, kpw, pf, nt, lds, st);
 }
-hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
-                       bool variants, hipStream_t st) {
-  return variants ? launch_prox_v<double, true>(d, n, blocks, threads, M, kpw, pf, lds, st)
-                  : launch_prox_v<double, false>(d, n, blocks, threads, M, kpw, pf, lds, st);
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, bool nt,
+                       size_t lds, bool variants, hipStream_t st) {
+  return variants ? launch_prox_v<double, true>(d, n, blocks, threads, M, kpw, pf, nt, lds, st)
+                  : launch_prox_v<double, false>(d, n, blocks, threads, M, kpw, pf, nt, lds, st);
 }
 
 }  // namespace segsalsa

@@ -59,10 +59,12 @@ inline int prox_max_threads_rt(bool fp64, int M, int kpw, bool pf = false) {
 // variants: the instantiation with the general Schatten p, the simplex g4 and the
 // primal-residual accumulation compiled in (required for descriptors with res_tile set)
 // pf: the prefetching build (prox_has_prefetch; only without variants)
-hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
-                       bool variants, hipStream_t st);
-hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, size_t lds,
-                       bool variants, hipStream_t st);
+// nt: the streaming build (nontemporal state accesses; only without variants
+// or prefetch, ignored otherwise)
+hipError_t launch_prox(const ProxArgs<float>* d, int n, int blocks, int threads, int M, int kpw, bool pf, bool nt,
+                       size_t lds, bool variants, hipStream_t st);
+hipError_t launch_prox(const ProxArgs<double>* d, int n, int blocks, int threads, int M, int kpw, bool pf, bool nt,
+                       size_t lds, bool variants, hipStream_t st);
 
 // FFT passes; narrow (FP64 only): the instantiation built for at most 512
 // threads per workgroup (threads must not exceed it)
