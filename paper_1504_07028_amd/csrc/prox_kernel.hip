@@ -49,11 +49,13 @@ namespace segsalsa {
 // second read of d2 (mostly served by the caches).
 //
 // NT (streaming, plain instantiation only): p_hat, d1, d3, d4 and d2 are
-// loaded and stored nontemporally.  A round touches each of them once, so
-// when the state of all images of a launch far exceeds the L2s and the
-// 256 MB MALL, caching them only evicts what the next kernels read again (the
-// partial sums, z); when it fits, the cached accesses keep it resident from
-// round to round.  The host chooses per round from the state's size.
+// loaded and stored nontemporally, and so are the grown-tile partial sums
+// written at the end (measured: the fold that reads them next runs as fast or
+// faster).  A round touches the state once, so when the state of all images
+// of a launch far exceeds the L2s and the 256 MB MALL, caching it only evicts
+// what the next kernels read again (z, the spectrum); when it fits, the
+// cached accesses keep it resident from round to round.  The host chooses per
+// round from the state's size.
 template <typename T, int M, int KPW, bool VAR, bool PF, bool NT>
 __global__ void __launch_bounds__((prox_max_threads<T, M, KPW, PF>()))
 prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
@@ -419,7 +421,7 @@ prox_rhs_kernel(const ProxArgs<T>* __restrict__ descs, int ndesc) {
     const int k = idx / plane;
     const int rem = idx - k * plane;
     const int er = rem / EC, ec = rem - er * EC;
-    out[((size_t)k * g.ER + er) * g.EC + ec] = acc[idx];
+    sst(out + ((size_t)k * g.ER + er) * g.EC + ec, acc[idx]);
   }
 }
 
