@@ -323,6 +323,26 @@ def hbm_copy_rate(torch, nbytes=2 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def hbm_stream_rate(S, torch, nbytes=2 << 30, reps=5):
+    """GB/s (read + write) of the library's streaming copy of nbytes (16-byte nontemporal loads and stores,
+    the access pattern of the prox kernel's streaming build): the practical ceiling of that kernel."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    S.segsalsa_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        S.segsalsa_stream_copy(src, dst)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def round_roofline(n_units, L, round_us, b=4):
     """Whole round (prox + the three FFT passes) against HBM: (4L + 15) words per pixel*class,
     the prox kernel's (4L + 9) plus the FFT passes' right-hand side and two spectrum round trips."""
@@ -454,6 +474,7 @@ def main():
     src_hash = kernel_source_hash()
     traffic = load_traffic(wl.name, "f32", src_hash)
     copy_gbs = hbm_copy_rate(torch)
+    stream_gbs = hbm_stream_rate(S, torch)
     value = res["f32"]["value"] if (z_err is None or z_err <= Z_TOL) else 0.0
     round_us = res["f32"]["ms_per_step"] * 1e3 / max(1, wl.iters)
     out = {
@@ -476,10 +497,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch_alg": bytes_launch,
                      "avg_launch_us": prox["avg_us"], "kernel_source_hash": src_hash,
-                     "frac_of_copy": achieved / copy_gbs},
+                     "frac_of_copy": achieved / copy_gbs, "frac_of_stream_copy": achieved / stream_gbs},
         "round_roofline": round_roofline(wl.n * wl.K, wl.L, round_us),
         "z_err_fp32_vs_fp64": z_err,
         "hbm_copy_gbs": copy_gbs,
+        "hbm_stream_copy_gbs": stream_gbs,
         "phases_f32_us": {k: round(v["avg_us"], 3) for k, v in res["f32"]["phases"].items()},
     }
     if "f64" in res:

@@ -392,7 +392,8 @@ segsalsa_status segsalsa_str_autotune(const segsalsa_problem *prob, segsalsa_pre
  * caller's stream immediately before and after each kernel launch.  Off by
  * default; enabling it adds two event records per launch.
  *   phases: 0 = fused proximity/multiplier/J^T kernel, 1 = fold + row DFT,
- *           2 = column DFT / symbol division / inverse column DFT,
+ *           2 = column half of the solve (the recursions, or column DFT /
+ *           symbol division / inverse column DFT),
  *           3 = inverse row DFT, 4 = reverse-sweep proximity kernel
  *           (segsalsa_str_backward; its solves count under 1-3).
  * segsalsa_profile_read waits for the recorded events, adds their elapsed
@@ -403,6 +404,18 @@ segsalsa_status segsalsa_str_autotune(const segsalsa_problem *prob, segsalsa_pre
 #define SEGSALSA_NUM_PHASES 5
 segsalsa_status segsalsa_profile_enable(int32_t on);
 segsalsa_status segsalsa_profile_read(double *ms, int64_t *launches, int32_t reset);
+
+/*
+ * Instrumentation (not part of the method), for callers that measure the
+ * memory system's streaming rate as the reference of the proximity kernel's
+ * roofline: copies `bytes` from src to dst (both DEVICE, caller-owned,
+ * 16-byte aligned, not overlapping; bytes a multiple of 16) with 16-byte
+ * nontemporal loads and stores, the access pattern of that kernel's
+ * streaming build.  Asynchronous on `stream`; INVALID_ARG for NULL, misaligned
+ * or overlapping buffers (checked on the host, nothing is launched).
+ */
+segsalsa_status segsalsa_stream_copy(const void *src /* DEVICE */, void *dst /* DEVICE */, size_t bytes,
+                                     hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -2288,6 +2288,18 @@ segsalsa_status segsalsa_str_backward(const segsalsa_problem* prob, segsalsa_pre
                      : backward_t<float>(gl, workspace, input, grad_z, grad_input, grad_lambda, grad_weights, stream);
 }
 
+segsalsa_status segsalsa_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+  g_last_error.clear();
+  if (bytes == 0) return SEGSALSA_OK;
+  if (!src || !dst) return fail(SEGSALSA_ERR_INVALID_ARG, "stream copy: NULL pointer");
+  if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+    return fail(SEGSALSA_ERR_INVALID_ARG, "stream copy: pointers and size must be multiples of 16 bytes");
+  const uintptr_t s0 = reinterpret_cast<uintptr_t>(src), d0 = reinterpret_cast<uintptr_t>(dst);
+  if (s0 < d0 + bytes && d0 < s0 + bytes) return fail(SEGSALSA_ERR_INVALID_ARG, "stream copy: buffers overlap");
+  const hipError_t e = launch_stream_copy(dst, src, bytes, stream);
+  return e == hipSuccess ? SEGSALSA_OK : hip_fail(e, "stream copy");
+}
+
 segsalsa_status segsalsa_profile_enable(int32_t on) {
   g_last_error.clear();
   std::lock_guard<std::mutex> lk(g_prof.mu);

@@ -7,6 +7,8 @@
 //   ||G x||^2 = 3 ||x||^2 + ||J x||^2 = 3 ||x||^2 + Wsum (||D_h x||^2 + ||D_v x||^2),
 // a local stencil because the periodic shifts P_j are orthogonal.
 // All sums are accumulated in FP64 and reduced in a fixed order.
+#include <algorithm>
+
 #include "segsalsa_internal.h"
 #include "segsalsa_kernels.h"
 
@@ -161,6 +163,33 @@ hipError_t launch_dual_res_t(const DiagArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, a.partial, kDiagBlocks, a.out, 1);
   return hipGetLastError();
 }
+// Streaming copy: 16-byte nontemporal loads and stores, four per thread in
+// flight, over a grid of a few workgroups per compute unit (the access
+// pattern of the prox kernel's streaming build, without its arithmetic).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) stream_copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                          size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 8);
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const u32x4*>(src),
+                     reinterpret_cast<u32x4*>(dst), n);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes % 16 == 0)
     return launch_copy_t(reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), bytes / 16, st);

@@ -298,5 +298,7 @@ hipError_t launch_adj_input(const AdjIOArgs<float>& a, hipStream_t st);
 hipError_t launch_adj_input(const AdjIOArgs<double>& a, hipStream_t st);
 hipError_t launch_adj_params(const double* gpart, int ntiles, int L, const AdjParamOut& o, hipStream_t st);
 hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t st);
+// bytes: a multiple of 16; both pointers 16-byte aligned
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 }  // namespace segsalsa

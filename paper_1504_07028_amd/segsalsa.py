@@ -122,6 +122,8 @@ def lib():
     L.segsalsa_profile_enable.restype = c_int32
     L.segsalsa_profile_read.argtypes = [POINTER(c_double), POINTER(ctypes.c_int64), c_int32]
     L.segsalsa_profile_read.restype = c_int32
+    L.segsalsa_stream_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+    L.segsalsa_stream_copy.restype = c_int32
     shape = [c_int32, c_int32, c_int32, c_int32, c_int32]
     L.segsalsa_tuning_set.argtypes = shape + [POINTER(segsalsa_tuning)]
     L.segsalsa_tuning_set.restype = c_int32
@@ -475,6 +477,15 @@ class SegSalsaSTR(torch.autograd.Function):
 
 
 PHASES = ("prox_rhs", "fold_row_dft", "col_solve", "row_idft", "adjoint_prox")
+
+
+def segsalsa_stream_copy(src, dst, stream=None):
+    """Copy the bytes of src into dst (device tensors of equal byte size, 16-byte multiples) with
+    nontemporal 16-byte loads and stores: the reference for the memory system's streaming rate."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _check(lib().segsalsa_stream_copy(_dev_ptr(src, "src"), _dev_ptr(dst, "dst"), nbytes, _stream(stream)))
 
 
 def segsalsa_profile_enable(on: bool):

@@ -414,3 +414,13 @@ def test_planner_prefers_vector_fold_tiles(clean_table):
         for prec, vec in ((0, 4), (1, 2)):
             plan, tuned = S.segsalsa_tuning_get(K, H, W, M, prec)
             assert not tuned and vector_fold_fits(W, M, plan["tile_cols"], vec), (K, H, W, M, prec, plan)
+
+
+def test_stream_copy_rejects_bad_buffers_on_the_host(S):
+    """The streaming copy checks its buffers before launching anything: NULL, misaligned, a size that is not
+    a multiple of 16 bytes, or overlapping ranges give INVALID_ARG; zero bytes is a no-op."""
+    lib = S.lib()
+    assert lib.segsalsa_stream_copy(None, None, 0, None) == 0
+    for src, dst, n in ((None, 4096, 64), (4096, None, 64), (4096 + 8, 1 << 20, 64), (4096, (1 << 20) + 4, 64),
+                        (4096, 1 << 20, 60), (4096, 4096 + 32, 64)):
+        assert lib.segsalsa_stream_copy(src, dst, n, None) == 1, (src, dst, n)   # INVALID_ARG

@@ -131,3 +131,16 @@ def test_clean_input_has_no_flags():
     probs, _, _, c = problem_inputs(8, 9, 3, 1, seed=6)
     _, _, _, st = gpu_solve(S, probs, c, 1, 1.0, 1.0, 1.0, 3, torch.float64, stats=True)
     assert st["flags"] == 0 and st["rounds_done"] == 3
+
+
+def test_stream_copy_moves_every_byte():
+    """The streaming copy (the bench's reference for the prox kernel's streaming build) copies exactly:
+    a size whose 16-byte words do not fill the four-deep unrolled loop, and one that does."""
+    S = need_gpu()
+    for n in (4 * 1000 + 4, 1 << 20):
+        src = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device="cuda")
+        dst = torch.zeros_like(src)
+        say(f"case stream copy {n * 4} bytes")
+        S.segsalsa_stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
